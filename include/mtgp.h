@@ -1,0 +1,232 @@
+/*
+ * mtgp.h -- C ABI of the MI355X (gfx950) MTGP32 bulk generator.
+ *
+ * Model (Passerat-Palmbach et al., ESM 2010):
+ *   - A generator is a seed status plus a parameterised status (Sec. 3.1):
+ *     here a uint32 seed plus an `mtgp_params` record.
+ *   - Every generator is an independent stream owned by one GPU thread group,
+ *     its state manipulated in on-chip shared memory (LDS) and kept in device
+ *     memory between calls (Sec. 2, Sec. 3.2).
+ *   - The CPU and GPU produce the same numbers (Sec. 3.2): every output of
+ *     this library is bit-identical to a plain CPU evaluation of the
+ *     definition below.
+ *
+ * Definition computed (the paper leaves the word-level recurrence to Saito's
+ * MTGP; this is the published MTGP32 form).  For a stream with N state words
+ * x_j .. x_{j+N-1}, N = floor(mexp/32)+1, W = N - pos:
+ *     X   = (x_j & mask) ^ x_{j+1};   X ^= X << sh1;
+ *     Y   = X ^ (x_{j+pos} >> sh2);   x_{j+N} = Y ^ rec_tbl[Y & 15];
+ *     H   = x_{j+pos-1};  H ^= H >> 16;  H ^= H >> 8;  t = H & 15;
+ *     u32 output j = x_{j+N} ^ tmp_tbl[t]
+ *     f32 output j = as_float((x_{j+N} >> 9) ^ flt_tbl[t]) - 1.0f   (in [0,1))
+ * Initial state from a seed (Mersenne Twister initialisation):
+ *     x_0 = seed;  x_i = 1812433253 * (x_{i-1} ^ (x_{i-1} >> 30)) + i.
+ *
+ * Conventions
+ *   - Device pointers (prefix d_) are allocated and owned by the caller; the
+ *     library borrows them for the duration of the call (and, for the
+ *     server, until mtgp_server_destroy).  Host pointers (prefix h_) are
+ *     read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls are asynchronous and stream-ordered unless stated otherwise.
+ *   - Every function returns MTGP_OK (0) or a negative MTGP_E* code; nothing
+ *     is launched when validation fails.  mtgp_last_error_detail() gives a
+ *     thread-local human-readable reason for the last failure.
+ *   - One parameter set (all streams passed to mtgp_init_states together)
+ *     shares one mexp in {3217, 11213, 23209, 44497}.
+ *   - Each call advances each touched stream by exactly the number of
+ *     outputs it produces, whatever the dtype.
+ */
+#ifndef MTGP_H
+#define MTGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Parameterised status of one generator (Sec. 3.1), 212 bytes, host side.
+ * rec_tbl: recursion table; tmp_tbl: uint32 tempering table; flt_tbl: float
+ * tempering table, each entry with sign 0 and exponent 0x7F (bits 31..23 ==
+ * 0x7F) so that the float lies in [1,2) before the subtraction of 1.0. */
+typedef struct mtgp_params {
+    uint32_t mexp, pos, sh1, sh2, mask;
+    uint32_t rec_tbl[16], tmp_tbl[16], flt_tbl[16];
+} mtgp_params;
+
+enum {
+    MTGP_OK = 0,
+    MTGP_EINVAL = -1,     /* bad argument or parameter set                 */
+    MTGP_ENOMEM = -2,     /* host allocation failed                        */
+    MTGP_EDEVICE = -3,    /* HIP runtime error                             */
+    MTGP_ETOOBIG = -4,    /* request larger than the server's output pool  */
+    MTGP_EAGAIN = -5,     /* server queue full / try again                 */
+    MTGP_ENOENT = -6,     /* unknown ticket                                */
+    MTGP_ECANCELED = -7,  /* request cancelled (server destroyed)          */
+    MTGP_ETIMEDOUT = -8   /* wait deadline passed                          */
+};
+
+enum { MTGP_U32 = 0, MTGP_F32 = 1 };
+
+/* Bytes of device memory one stream's parameter block takes (256). */
+#define MTGP_DEVICE_PARAM_BYTES 256
+
+/* N = floor(mexp/32)+1 for a supported mexp, else MTGP_EINVAL. */
+int mtgp_state_words(uint32_t mexp);
+
+/* Validates n host parameter sets: supported mexp, one mexp for all, mask ==
+ * 0xFFFFFFFF << (32N - mexp), 1 <= pos <= N-2, sh1, sh2 <= 31, float-table
+ * exponent bits 0x7F.  MTGP_OK or MTGP_EINVAL (detail names stream + field). */
+int mtgp_check_params(const mtgp_params *h_params, int n_streams);
+
+/* Seed status -> initial state for every stream (Sec. 3.1, Sec. 5.1).
+ *   h_params   : n_streams parameter sets (validated first).
+ *   h_seeds    : n_streams seeds (uint32).
+ *   d_params   : device buffer of n_streams * MTGP_DEVICE_PARAM_BYTES bytes,
+ *                written with the library's packed parameter layout.
+ *   d_states   : device buffer of n_streams * state_stride uint32; row k
+ *                receives x_0..x_{N-1} of stream k.
+ *   state_stride >= N (words between consecutive rows).
+ * Synchronises `stream` before returning (the host staging buffer is freed).
+ * The library keeps a host copy of the parameter sets, keyed by d_params,
+ * which generate/batch/server calls use for launch planning. */
+int mtgp_init_states(const mtgp_params *h_params, const uint32_t *h_seeds,
+                     int n_streams, void *d_params, uint32_t *d_states,
+                     int state_stride, void *stream);
+
+/* Uploads parameter sets without touching states (e.g. before importing
+ * checkpointed states).  Same layout and synchronisation as above. */
+int mtgp_load_params(const mtgp_params *h_params, int n_streams,
+                     void *d_params, void *stream);
+
+/* Forgets the host copy kept for d_params (call before freeing it). */
+int mtgp_release_params(const void *d_params);
+
+/* Plain bulk generation, one launch, one thread group per stream (Sec. 2):
+ * advances streams 0..n_streams-1 of the set by `count_per_stream` outputs
+ * each and writes output j of stream k to d_out[k * count_per_stream + j]
+ * (stream-major, 64-bit indexing).  d_states rows are updated in place.
+ * d_out must hold n_streams * count_per_stream words. */
+int mtgp_generate_u32(const void *d_params, uint32_t *d_states,
+                      int state_stride, int n_streams,
+                      uint64_t count_per_stream, uint32_t *d_out, void *stream);
+int mtgp_generate_f32(const void *d_params, uint32_t *d_states,
+                      int state_stride, int n_streams,
+                      uint64_t count_per_stream, float *d_out, void *stream);
+
+/* One request of a batch: advance `stream_id` by `count` outputs of `dtype`
+ * and write them contiguously at d_out. */
+typedef struct mtgp_work {
+    int32_t stream_id;
+    uint32_t dtype;       /* MTGP_U32 or MTGP_F32 */
+    uint64_t count;
+    void *d_out;
+} mtgp_work;
+
+/* Workspace bytes mtgp_generate_batch needs for n_items requests. */
+size_t mtgp_batch_workspace_bytes(int n_items);
+
+/* Batched generation: one persistent kernel advances many streams with
+ * uneven lengths and mixed dtypes in a single launch, replayed from a
+ * hipGraph captured once per (buffers, item count, tuning).  Items are
+ * scheduled longest-critical-path first.  A stream id may appear at most
+ * once per call.  d_workspace: mtgp_batch_workspace_bytes(n_items) bytes of
+ * device memory the caller owns (work list + counters).  Asynchronous. */
+int mtgp_generate_batch(const void *d_params, uint32_t *d_states,
+                        int state_stride, const mtgp_work *h_items,
+                        int n_items, void *d_workspace, void *stream);
+
+/* Launch tuning for one mexp: threads per stream (64 = one wave per stream,
+ * several streams per workgroup; 256/512/1024 = one stream per workgroup),
+ * outputs per lane per step, and workgroup size. */
+typedef struct mtgp_tuning {
+    int threads_per_stream;
+    int outputs_per_lane;
+    int workgroup_size;
+} mtgp_tuning;
+
+int mtgp_get_tuning(uint32_t mexp, mtgp_tuning *out);
+int mtgp_set_tuning(uint32_t mexp, const mtgp_tuning *t);
+/* Number of candidate tunings compiled in for mexp, and candidate i. */
+int mtgp_tuning_candidates(uint32_t mexp, mtgp_tuning *out, int max_out);
+
+/* Autotuner: times every compiled candidate on the given batch (run on a
+ * scratch copy of the states, so the caller's states are untouched), keeps
+ * the fastest as the tuning for this mexp and returns it in *best.
+ * d_scratch: n_streams * state_stride * 4 bytes + mtgp_batch_workspace_bytes
+ * (n_items).  Output buffers named by the items are overwritten.
+ * Synchronises `stream`.  h_ms (may be NULL) receives up to max_out
+ * per-candidate times in ms, in mtgp_tuning_candidates order. */
+int mtgp_autotune(const void *d_params, const uint32_t *d_states,
+                  int state_stride, const mtgp_work *h_items, int n_items,
+                  void *d_scratch, int reps, void *stream, mtgp_tuning *best,
+                  float *h_ms, int max_out);
+
+/* Checkpoint: copy n_streams state rows device -> host (h_out holds
+ * n_streams * N words, densely packed) and back.  Synchronise `stream`.
+ * This is the paper's persistence of generator state in global memory
+ * between launches (Sec. 2). */
+int mtgp_state_export(const void *d_params, const uint32_t *d_states,
+                      int state_stride, int n_streams, uint32_t *h_out,
+                      void *stream);
+int mtgp_state_import(const void *d_params, uint32_t *d_states,
+                      int state_stride, int n_streams, const uint32_t *h_in,
+                      void *stream);
+
+/* Store-only fill of n words (bandwidth reference for the roofline). */
+int mtgp_fill_u32(uint32_t *d_out, uint64_t n_words, uint32_t value,
+                  void *stream);
+
+/* ------------------------------------------------------------ serving --
+ * A request loop over resident stream states: requests (stream, count,
+ * dtype) are admitted while their output bytes fit a caller-owned device
+ * pool, served in submission order per stream, batched with whatever else
+ * is waiting or running, and launched through the persistent kernel on
+ * several HIP streams so that work admitted later overlaps earlier work.
+ * Each result is exactly the next `count` outputs of its stream. */
+typedef struct mtgp_server mtgp_server;
+
+typedef struct mtgp_server_opts {
+    int max_inflight_batches;  /* concurrent launches (HIP streams), >= 1  */
+    int max_batch_items;       /* requests per launch                      */
+    int max_queue;             /* pending requests before MTGP_EAGAIN      */
+    uint64_t batch_window_ns;  /* wait this long for more requests when a
+                                  launch slot is free but the queue is short */
+} mtgp_server_opts;
+
+enum { MTGP_PENDING = 0, MTGP_DONE = 1, MTGP_FAILED = 2 };
+
+int mtgp_server_create(const void *d_params, uint32_t *d_states,
+                       int state_stride, int n_streams, void *d_pool,
+                       uint64_t pool_bytes, const mtgp_server_opts *opts,
+                       mtgp_server **out);
+/* Queue a request; *ticket identifies it.  MTGP_ETOOBIG if count*4 bytes
+ * exceed the pool, MTGP_EAGAIN if the queue is full. Thread-safe. */
+int mtgp_submit(mtgp_server *srv, int32_t stream_id, uint64_t count,
+                int dtype, uint64_t *ticket);
+/* Non-blocking status; *d_result is the device address of the output once
+ * MTGP_DONE (valid until mtgp_release). */
+int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state,
+              const void **d_result);
+/* Block until done or timeout (0 = forever).  MTGP_ETIMEDOUT on deadline. */
+int mtgp_wait(mtgp_server *srv, uint64_t ticket, uint64_t timeout_ns);
+/* Return the request's output bytes to the pool and forget the ticket. */
+int mtgp_release(mtgp_server *srv, uint64_t ticket);
+/* Per-request timestamps in ns since server creation: submitted, admitted
+ * (pool bytes granted), launched, completed (observed by the server). */
+int mtgp_request_times(mtgp_server *srv, uint64_t ticket, uint64_t *t_submit,
+                       uint64_t *t_admit, uint64_t *t_launch,
+                       uint64_t *t_done);
+/* Stops the loop; queued requests never admitted end as MTGP_ECANCELED,
+ * in-flight launches are waited for. */
+int mtgp_server_destroy(mtgp_server *srv);
+
+const char *mtgp_strerror(int code);
+const char *mtgp_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MTGP_H */

@@ -1,0 +1,315 @@
+"""ctypes binding of the C ABI in ``include/mtgp.h``.
+
+Argument marshalling only: every step of generation runs in the HIP library
+(``_build/libmtgp.so``).  Device buffers are passed as raw addresses; torch
+tensors are accepted wherever a device buffer is expected and only their
+``data_ptr()`` is used.  Streams are ``torch.cuda.Stream`` objects, raw
+``hipStream_t`` integers, or None (the current torch stream).
+
+If the library has not been built, the first call raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libmtgp.so")
+PARAM_WORDS = 53
+DEVICE_PARAM_BYTES = 256
+U32, F32 = 0, 1
+PENDING, DONE, FAILED = 0, 1, 2
+
+OK, EINVAL, ENOMEM, EDEVICE, ETOOBIG, EAGAIN, ENOENT, ECANCELED, ETIMEDOUT = (
+    0, -1, -2, -3, -4, -5, -6, -7, -8)
+
+
+class MTGPError(RuntimeError):
+    def __init__(self, code: int, func: str, detail: str):
+        super().__init__("%s failed: %s (%d): %s" % (func, _strerror(code), code, detail))
+        self.code = code
+
+
+class Work(ctypes.Structure):
+    _fields_ = [("stream_id", ctypes.c_int32), ("dtype", ctypes.c_uint32),
+                ("count", ctypes.c_uint64), ("d_out", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("threads_per_stream", ctypes.c_int), ("outputs_per_lane", ctypes.c_int),
+                ("workgroup_size", ctypes.c_int)]
+
+    def as_tuple(self):
+        return (self.threads_per_stream, self.outputs_per_lane, self.workgroup_size)
+
+    def __repr__(self):
+        return "Tuning(tps=%d, k=%d, wg=%d)" % self.as_tuple()
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_inflight_batches", ctypes.c_int), ("max_batch_items", ctypes.c_int),
+                ("max_queue", ctypes.c_int), ("batch_window_ns", ctypes.c_uint64)]
+
+
+_lib = None
+_lock = threading.Lock()
+
+_VP, _U32P, _U64P, _INTP = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int))
+_SIGS = {
+    "mtgp_state_words": ([ctypes.c_uint32], ctypes.c_int),
+    "mtgp_check_params": ([_VP, ctypes.c_int], ctypes.c_int),
+    "mtgp_init_states": ([_VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "mtgp_load_params": ([_VP, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_release_params": ([_VP], ctypes.c_int),
+    "mtgp_generate_u32": ([_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _VP, _VP],
+                          ctypes.c_int),
+    "mtgp_generate_f32": ([_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _VP, _VP],
+                          ctypes.c_int),
+    "mtgp_batch_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
+    "mtgp_generate_batch": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP, _VP],
+                            ctypes.c_int),
+    "mtgp_get_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "mtgp_set_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "mtgp_tuning_candidates": ([ctypes.c_uint32, ctypes.POINTER(Tuning), ctypes.c_int],
+                               ctypes.c_int),
+    "mtgp_autotune": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP,
+                       ctypes.c_int, _VP, ctypes.POINTER(Tuning),
+                       ctypes.POINTER(ctypes.c_float), ctypes.c_int], ctypes.c_int),
+    "mtgp_state_export": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_state_import": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_fill_u32": ([_VP, ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
+    "mtgp_server_create": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_uint64,
+                            ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)],
+                           ctypes.c_int),
+    "mtgp_submit": ([_VP, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _U64P], ctypes.c_int),
+    "mtgp_poll": ([_VP, ctypes.c_uint64, _INTP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "mtgp_wait": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
+    "mtgp_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
+    "mtgp_request_times": ([_VP, ctypes.c_uint64, _U64P, _U64P, _U64P, _U64P], ctypes.c_int),
+    "mtgp_server_destroy": ([_VP], ctypes.c_int),
+    "mtgp_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "mtgp_last_error_detail": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """The loaded HIP library; raises if it was never built."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(
+                    "MTGP HIP library not built (%s missing); run "
+                    "`python -m paper_1501_07701_amd.build` or __graft_entry__.build()" % LIB_PATH)
+            L = ctypes.CDLL(LIB_PATH)
+            for name, (args, res) in _SIGS.items():
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = res
+            _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().mtgp_strerror(code).decode()
+    except Exception:  # library missing while formatting an error
+        return "error"
+
+
+def _check(rc: int, func: str) -> int:
+    if rc < 0:
+        raise MTGPError(rc, func, lib().mtgp_last_error_detail().decode())
+    return rc
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    raise TypeError("cannot take the address of %r" % type(x))
+
+
+def _stream(s) -> int:
+    if s is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _host_params(params: np.ndarray) -> np.ndarray:
+    p = np.ascontiguousarray(params, dtype=np.uint32)
+    if p.ndim != 2 or p.shape[1] != PARAM_WORDS:
+        raise ValueError("params must be (n, %d) uint32" % PARAM_WORDS)
+    return p
+
+
+# ----------------------------------------------------------------- core ---
+
+def state_words(mexp: int) -> int:
+    return _check(lib().mtgp_state_words(mexp), "mtgp_state_words")
+
+
+def check_params(params: np.ndarray) -> None:
+    p = _host_params(params)
+    _check(lib().mtgp_check_params(_ptr(p), p.shape[0]), "mtgp_check_params")
+
+
+def init_states(params: np.ndarray, seeds: np.ndarray, d_params, d_states, stride: int,
+                stream=None) -> None:
+    p = _host_params(params)
+    s = np.ascontiguousarray(seeds, dtype=np.uint32)
+    if s.shape != (p.shape[0],):
+        raise ValueError("one seed per stream")
+    _check(lib().mtgp_init_states(_ptr(p), _ptr(s), p.shape[0], _ptr(d_params), _ptr(d_states),
+                                  stride, _stream(stream)), "mtgp_init_states")
+
+
+def load_params(params: np.ndarray, d_params, stream=None) -> None:
+    p = _host_params(params)
+    _check(lib().mtgp_load_params(_ptr(p), p.shape[0], _ptr(d_params), _stream(stream)),
+           "mtgp_load_params")
+
+
+def release_params(d_params) -> None:
+    _check(lib().mtgp_release_params(_ptr(d_params)), "mtgp_release_params")
+
+
+def generate(d_params, d_states, stride: int, n_streams: int, count: int, d_out,
+             dtype: int = U32, stream=None) -> None:
+    fn = lib().mtgp_generate_f32 if dtype == F32 else lib().mtgp_generate_u32
+    _check(fn(_ptr(d_params), _ptr(d_states), stride, n_streams, count, _ptr(d_out),
+              _stream(stream)), "mtgp_generate_%s" % ("f32" if dtype == F32 else "u32"))
+
+
+def batch_workspace_bytes(n_items: int) -> int:
+    return int(lib().mtgp_batch_workspace_bytes(n_items))
+
+
+def make_work(items) -> ctypes.Array:
+    """items: iterable of (stream_id, dtype, count, d_out)."""
+    items = list(items)
+    arr = (Work * max(len(items), 1))()
+    for i, (sid, dt, cnt, out) in enumerate(items):
+        arr[i] = Work(int(sid), int(dt), int(cnt), _ptr(out))
+    return arr, len(items)
+
+
+def generate_batch(d_params, d_states, stride: int, items, d_workspace, stream=None) -> None:
+    arr, n = items if isinstance(items, tuple) else make_work(items)
+    _check(lib().mtgp_generate_batch(_ptr(d_params), _ptr(d_states), stride, arr, n,
+                                     _ptr(d_workspace), _stream(stream)), "mtgp_generate_batch")
+
+
+def get_tuning(mexp: int) -> Tuning:
+    t = Tuning()
+    _check(lib().mtgp_get_tuning(mexp, ctypes.byref(t)), "mtgp_get_tuning")
+    return t
+
+
+def set_tuning(mexp: int, tps: int, k: int, wg: int) -> None:
+    t = Tuning(tps, k, wg)
+    _check(lib().mtgp_set_tuning(mexp, ctypes.byref(t)), "mtgp_set_tuning")
+
+
+def tuning_candidates(mexp: int):
+    n = _check(lib().mtgp_tuning_candidates(mexp, None, 0), "mtgp_tuning_candidates")
+    arr = (Tuning * n)()
+    _check(lib().mtgp_tuning_candidates(mexp, arr, n), "mtgp_tuning_candidates")
+    return [arr[i] for i in range(n)]
+
+
+def autotune(d_params, d_states, stride: int, items, d_scratch, reps: int = 2, stream=None):
+    """Times every compiled candidate on this batch; returns (best, {tuple: ms})."""
+    arr, n = items if isinstance(items, tuple) else make_work(items)
+    best = Tuning()
+    cands = None
+    ms = (ctypes.c_float * 64)()
+    _check(lib().mtgp_autotune(_ptr(d_params), _ptr(d_states), stride, arr, n, _ptr(d_scratch),
+                               reps, _stream(stream), ctypes.byref(best), ms, 64),
+           "mtgp_autotune")
+    # candidate order is mtgp_tuning_candidates order for this mexp
+    return best, ms
+
+
+def state_export(d_params, d_states, stride: int, n_streams: int, n_words: int,
+                 stream=None) -> np.ndarray:
+    out = np.zeros((n_streams, n_words), dtype=np.uint32)
+    _check(lib().mtgp_state_export(_ptr(d_params), _ptr(d_states), stride, n_streams, _ptr(out),
+                                   _stream(stream)), "mtgp_state_export")
+    return out
+
+
+def state_import(d_params, d_states, stride: int, host_states: np.ndarray, stream=None) -> None:
+    h = np.ascontiguousarray(host_states, dtype=np.uint32)
+    _check(lib().mtgp_state_import(_ptr(d_params), _ptr(d_states), stride, h.shape[0], _ptr(h),
+                                   _stream(stream)), "mtgp_state_import")
+
+
+def fill_u32(d_out, n_words: int, value: int, stream=None) -> None:
+    _check(lib().mtgp_fill_u32(_ptr(d_out), n_words, value & 0xFFFFFFFF, _stream(stream)),
+           "mtgp_fill_u32")
+
+
+# ------------------------------------------------------------- helpers ---
+
+class Generators:
+    """A parameter set with its device-resident states, allocated with torch.
+
+    params: (n, 53) uint32 host array; seeds: (n,) uint32."""
+
+    def __init__(self, params: np.ndarray, seeds: np.ndarray, device="cuda", stride=None):
+        import torch
+        self.params = _host_params(params)
+        self.n = self.params.shape[0]
+        self.mexp = int(self.params[0, 0])
+        self.N = state_words(self.mexp)
+        self.stride = int(stride) if stride else self.N
+        self.device = torch.device(device)
+        self.d_params = torch.empty(self.n * DEVICE_PARAM_BYTES, dtype=torch.uint8,
+                                    device=self.device)
+        self.d_states = torch.empty(self.n * self.stride, dtype=torch.int32, device=self.device)
+        init_states(self.params, seeds, self.d_params, self.d_states, self.stride)
+
+    def generate(self, count: int, dtype: int = U32, out=None, n_streams=None, stream=None):
+        import torch
+        n = self.n if n_streams is None else n_streams
+        if out is None:
+            out = torch.empty(n * count, dtype=torch.float32 if dtype == F32 else torch.int32,
+                              device=self.device)
+        generate(self.d_params, self.d_states, self.stride, n, count, out, dtype, stream)
+        return out
+
+    def states_host(self) -> np.ndarray:
+        return state_export(self.d_params, self.d_states, self.stride, self.n, self.N)
+
+    def load_states(self, host_states: np.ndarray) -> None:
+        state_import(self.d_params, self.d_states, self.stride, host_states)
+
+    def workspace(self, n_items: int):
+        import torch
+        return torch.empty(batch_workspace_bytes(n_items), dtype=torch.uint8, device=self.device)
+
+    def batch(self, items, workspace=None, stream=None):
+        items = list(items)
+        ws = self.workspace(len(items)) if workspace is None else workspace
+        generate_batch(self.d_params, self.d_states, self.stride, items, ws, stream)
+        return ws
+
+    def close(self):
+        try:
+            release_params(self.d_params)
+        except MTGPError:
+            pass

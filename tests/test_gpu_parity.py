@@ -1,0 +1,306 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Small cases span several steps, buffer compactions and ragged tails, for
+every supported mexp and every compiled launch tuning; the full-size
+workloads are checked on sampled streams (the oracle runs each sampled
+stream from its initial state) plus properties that hold at any size.
+Tolerance: none.  uint32 outputs, float32 bit patterns and final states must
+be identical.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_07701_amd import mtgp, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    mtgp.lib()  # fail loudly if the HIP library is missing
+    return t
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _oracle_run(params, seeds, counts, as_float):
+    """Run the oracle per stream from its seed over successive calls.
+    counts: list of per-call counts; as_float: per-call flags.
+    Returns (list of per-call outputs as uint32 views [k][call], final states)."""
+    n = params.shape[0]
+    N = int(params[0, 0]) // 32 + 1
+    outs = [[] for _ in range(n)]
+    states = np.stack([oracle.seed(int(s), N) for s in seeds])
+    for c, f in zip(counts, as_float):
+        res, states = oracle.generate_many(params, states, c, f, threads=8)
+        for k in range(n):
+            outs[k].append(np.asarray(res[k]).view(np.uint32))
+    return outs, states
+
+
+def _edge_params(mexp, master):
+    """Random sets plus the degenerate corners: W = 2, W = N-1, sh1 = 0,
+    sh2 = 0, both shifts 31."""
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 8, master)
+    p[0, 1] = N - 2          # pos = N-2  -> W = 2
+    p[1, 1] = 1              # pos = 1    -> W = N-1
+    p[2, 2] = 0              # sh1 = 0
+    p[3, 3] = 0              # sh2 = 0
+    p[4, 2], p[4, 3] = 31, 31
+    p[5, 1] = N - 3          # W = 3
+    p[6, 1] = max(1, N - 65)  # W = 65 (one past a wave)
+    return p
+
+
+@pytest.mark.parametrize("mexp", workloads.SUPPORTED_MEXP)
+def test_plain_ragged_calls_all_mexp(torch, mexp):
+    _say("case plain_ragged mexp=%d" % mexp)
+    p = _edge_params(mexp, 0xABC0 + mexp)
+    seeds = np.array([0, 1, 2, 3, 5489, 0xFFFFFFFF, 77, 123456], dtype=np.uint32)
+    N = mexp // 32 + 1
+    calls = [1, 2, 63, 65, 3, N, 1000, 4097, 2 * N + 5]
+    flts = [False, True, False, True, False, False, True, False, True]
+    g = mtgp.Generators(p, seeds)
+    got = [[] for _ in range(p.shape[0])]
+    for c, f in zip(calls, flts):
+        out = g.generate(c, mtgp.F32 if f else mtgp.U32)
+        h = _host(out).reshape(p.shape[0], c)
+        for k in range(p.shape[0]):
+            got[k].append(h[k])
+    torch.cuda.synchronize()
+    exp, exp_states = _oracle_run(p, seeds, calls, flts)
+    for k in range(p.shape[0]):
+        for i in range(len(calls)):
+            assert np.array_equal(got[k][i], exp[k][i]), (mexp, k, i)
+    assert np.array_equal(g.states_host(), exp_states)
+    g.close()
+
+
+@pytest.mark.parametrize("mexp", [11213, 44497])
+def test_every_compiled_tuning_gives_identical_output(torch, mexp):
+    _say("case tunings mexp=%d" % mexp)
+    p = _edge_params(mexp, 0x51 + mexp)
+    seeds = np.arange(1, 9, dtype=np.uint32)
+    count = 3001
+    exp, exp_states = _oracle_run(p, seeds, [count, 517], [False, True])
+    t0 = mtgp.get_tuning(mexp)
+    try:
+        for cand in mtgp.tuning_candidates(mexp):
+            _say("  tuning", cand)
+            mtgp.set_tuning(mexp, *cand.as_tuple())
+            g = mtgp.Generators(p, seeds)
+            a = _host(g.generate(count, mtgp.U32)).reshape(8, count)
+            b = _host(g.generate(517, mtgp.F32)).reshape(8, 517)
+            for k in range(8):
+                assert np.array_equal(a[k], exp[k][0]), (cand, k)
+                assert np.array_equal(b[k], exp[k][1]), (cand, k)
+            assert np.array_equal(g.states_host(), exp_states), cand
+            # the batch path with the same tuning
+            g2 = mtgp.Generators(p, seeds)
+            outs = [torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(8)]
+            g2.batch([(k, mtgp.U32, count, outs[k]) for k in range(8)])
+            for k in range(8):
+                assert np.array_equal(_host(outs[k]), exp[k][0]), ("batch", cand, k)
+            g.close()
+            g2.close()
+    finally:
+        mtgp.set_tuning(mexp, *t0.as_tuple())
+
+
+def test_c1_full(torch):
+    """4 streams x 2^20 uint32, seeds 1..4, full comparison; then 2^20 more
+    as float32 continuing the streams."""
+    _say("case C1 full")
+    params, seeds = workloads.config_inputs("C1")
+    count = workloads.CONFIGS["C1"]["count"]
+    g = mtgp.Generators(params, seeds)
+    u = _host(g.generate(count, mtgp.U32)).reshape(4, count)
+    f = _host(g.generate(count, mtgp.F32)).reshape(4, count)
+    exp, exp_states = _oracle_run(params, seeds, [count, count], [False, True])
+    for k in range(4):
+        assert np.array_equal(u[k], exp[k][0]), k
+        assert np.array_equal(f[k], exp[k][1]), k
+    assert np.array_equal(g.states_host(), exp_states)
+    g.close()
+
+
+def test_seed_zero_and_state_roundtrip(torch):
+    _say("case seed0 + export/import")
+    p = workloads.make_params(3217, 3, 99)
+    seeds = np.zeros(3, dtype=np.uint32)
+    g = mtgp.Generators(p, seeds)
+    st0 = g.states_host()
+    for k in range(3):
+        assert np.array_equal(st0[k], oracle.seed(0, 101))
+    a = _host(g.generate(5000)).reshape(3, 5000)
+    mid = g.states_host()
+    b = _host(g.generate(777)).reshape(3, 777)
+    g.load_states(mid)                      # checkpoint restore
+    b2 = _host(g.generate(777)).reshape(3, 777)
+    assert np.array_equal(b, b2)
+    exp, _ = _oracle_run(p, seeds, [5000, 777], [False, False])
+    for k in range(3):
+        assert np.array_equal(a[k], exp[k][0]) and np.array_equal(b[k], exp[k][1])
+    g.close()
+
+
+def test_batch_uneven_mixed_with_replays(torch):
+    """Persistent kernel + hipGraph: uneven lengths, mixed dtypes, a subset
+    of streams, three replays of the same graph continuing the streams."""
+    _say("case batch uneven")
+    mexp = 23209
+    p = workloads.make_params(mexp, 40, 0xBA7C)
+    seeds = np.arange(1, 41, dtype=np.uint32)
+    rng = np.random.default_rng(4)
+    sel = rng.choice(40, 25, replace=False)
+    lens = rng.integers(1, 20000, 25)
+    lens[0], lens[1] = 1, 0     # zero-length items are skipped
+    dts = rng.integers(0, 2, 25)
+    g = mtgp.Generators(p, seeds)
+    ws = g.workspace(25)
+    outs = [torch.empty(max(int(L), 1), dtype=torch.int32, device="cuda") for L in lens]
+    items = [(int(s), int(d), int(L), o) for s, d, L, o in zip(sel, dts, lens, outs)]
+    got = []
+    for rep in range(3):
+        g.batch(items, ws)
+        got.append([_host(o)[:int(L)].copy() for o, L in zip(outs, lens)])
+    # oracle: each selected stream advanced three times
+    N = mexp // 32 + 1
+    states = np.stack([oracle.seed(int(s), N) for s in seeds])
+    for rep in range(3):
+        for j, (s, d, L) in enumerate(zip(sel, dts, lens)):
+            o, states[s] = oracle.generate(p[s], states[s], int(L), bool(d))
+            assert np.array_equal(got[rep][j], np.asarray(o).view(np.uint32)), (rep, j)
+    assert np.array_equal(g.states_host(), states)
+    g.close()
+
+
+def test_batch_rejects_duplicate_streams(torch):
+    p = workloads.make_params(11213, 4, 1)
+    g = mtgp.Generators(p, np.arange(4, dtype=np.uint32))
+    o = torch.empty(16, dtype=torch.int32, device="cuda")
+    with pytest.raises(mtgp.MTGPError) as e:
+        g.batch([(1, 0, 8, o), (1, 0, 8, o)])
+    assert "twice" in str(e.value)
+    g.close()
+
+
+def test_fill(torch):
+    x = torch.zeros(1 << 20 | 3, dtype=torch.int32, device="cuda")
+    mtgp.fill_u32(x, x.numel(), 0xDEADBEEF)
+    assert np.all(_host(x) == 0xDEADBEEF)
+
+
+def test_autotune_keeps_results_identical(torch):
+    _say("case autotune")
+    mexp = 11213
+    p = workloads.make_params(mexp, 32, 0x7777)
+    seeds = np.arange(1, 33, dtype=np.uint32)
+    g = mtgp.Generators(p, seeds)
+    before = g.states_host()
+    outs = [torch.empty(4096, dtype=torch.int32, device="cuda") for _ in range(32)]
+    items = [(k, k & 1, 4096, outs[k]) for k in range(32)]
+    scratch = torch.empty(32 * 351 * 4 + 256 + mtgp.batch_workspace_bytes(32),
+                          dtype=torch.uint8, device="cuda")
+    t0 = mtgp.get_tuning(mexp)
+    best, _ = mtgp.autotune(g.d_params, g.d_states, g.stride, items, scratch, reps=1)
+    assert np.array_equal(g.states_host(), before)   # caller's states untouched
+    assert mtgp.get_tuning(mexp).as_tuple() == best.as_tuple()
+    g.batch(items)
+    exp, _ = _oracle_run(p, seeds, [4096], [False])
+    for k in range(0, 32, 2):
+        assert np.array_equal(_host(outs[k]), exp[k][0])
+    mtgp.set_tuning(mexp, *t0.as_tuple())
+    g.close()
+
+
+# ------------------------------------------------------- full-size runs ---
+
+def test_c2_full_size_sampled(torch):
+    """128 streams x 2^24 as uint32, then as float32 from the same initial
+    states; sampled streams against the oracle, the float identity
+    bits(f + 1) == 0x3F800000 | (u >> 9) on every output."""
+    _say("case C2 full size")
+    params, seeds = workloads.config_inputs("C2")
+    count = workloads.CONFIGS["C2"]["count"]
+    g = mtgp.Generators(params, seeds)
+    init = g.states_host()
+    u = g.generate(count, mtgp.U32)
+    end_u = g.states_host()
+    g.load_states(init)
+    f = g.generate(count, mtgp.F32)
+    assert np.array_equal(g.states_host(), end_u)
+    ident = (f + 1.0).view(torch.int32) == (torch.bitwise_right_shift(u, 9) & 0x7FFFFF | 0x3F800000)
+    assert bool(ident.all())
+    sample = [0, 37, 127]
+    exp, exp_states = _oracle_run(params[sample], seeds[sample], [count], [False])
+    for j, k in enumerate(sample):
+        assert np.array_equal(_host(u[k * count:(k + 1) * count]), exp[j][0]), k
+        assert np.array_equal(end_u[k], exp_states[j])
+    g.close()
+
+
+def test_c3_full_size_sampled(torch):
+    """4096 streams x 2^20 uint32 in one persistent graph launch (16 GiB)."""
+    _say("case C3 full size")
+    params, seeds = workloads.config_inputs("C3")
+    count = workloads.CONFIGS["C3"]["count"]
+    n = params.shape[0]
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    items = [(k, mtgp.U32, count, out.data_ptr() + 4 * k * count) for k in range(n)]
+    g.batch(items)
+    torch.cuda.synchronize()
+    W = 726 - params[:, 1].astype(np.int64)
+    sample = sorted({int(np.argmin(W)), int(np.argmax(W)), 0, 1, 2049, 4095})
+    exp, exp_states = _oracle_run(params[sample], seeds[sample], [count], [False])
+    st = g.states_host()
+    for j, k in enumerate(sample):
+        assert np.array_equal(_host(out[k * count:(k + 1) * count]), exp[j][0]), k
+        assert np.array_equal(st[k], exp_states[j]), k
+    del out
+    g.close()
+
+
+def test_c4_full_size_sampled(torch):
+    """1024 streams, lengths log-uniform in [2^10, 2^24], dtype 50/50, one
+    launch; sampled streams (longest, shortest, smallest W, random)."""
+    _say("case C4 full size")
+    params, seeds = workloads.config_inputs("C4")
+    lens, dts = workloads.uneven_batch("C4")
+    n = params.shape[0]
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
+    base = out.data_ptr()
+    items = [(k, int(dts[k]), int(lens[k]), base + 4 * int(offs[k])) for k in range(n)]
+    g.batch(items)
+    torch.cuda.synchronize()
+    W = 1391 - params[:, 1].astype(np.int64)
+    sample = sorted({int(np.argmax(lens)), int(np.argmin(lens)), int(np.argmin(W)), 5, 700})
+    st = g.states_host()
+    N = 1391
+    for k in sample:
+        o, s_end = oracle.generate(params[k], oracle.seed(int(seeds[k]), N), int(lens[k]),
+                                   bool(dts[k]))
+        got = _host(out[int(offs[k]):int(offs[k + 1])])
+        assert np.array_equal(got, np.asarray(o).view(np.uint32)), k
+        assert np.array_equal(st[k], s_end), k
+    del out
+    g.close()
