@@ -96,6 +96,12 @@ int mtgp_init_states(const mtgp_params *h_params, const uint32_t *h_seeds,
                      int n_streams, void *d_params, uint32_t *d_states,
                      int state_stride, void *stream);
 
+/* Re-seeds streams 0..n_streams-1 from the seeds stored in d_params by
+ * mtgp_init_states (device only, asynchronous): the states return to the
+ * streams' seed status (Sec. 3.1). */
+int mtgp_seed_states(const void *d_params, uint32_t *d_states, int state_stride,
+                     int n_streams, void *stream);
+
 /* Uploads parameter sets without touching states (e.g. before importing
  * checkpointed states).  Same layout and synchronisation as above. */
 int mtgp_load_params(const mtgp_params *h_params, int n_streams,

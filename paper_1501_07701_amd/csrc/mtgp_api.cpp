@@ -462,6 +462,18 @@ int mtgp_init_states(const mtgp_params *h_params, const uint32_t *h_seeds, int n
     return MTGP_OK;
 }
 
+int mtgp_seed_states(const void *d_params, uint32_t *d_states, int state_stride, int n_streams,
+                     void *stream) {
+    auto ps = lookup_params(d_params, n_streams);
+    if (!ps) return MTGP_EINVAL;
+    if (n_streams <= 0 || !d_states || state_stride < ps->N)
+        return fail(MTGP_EINVAL, "bad states (n=%d, stride=%d, N=%d)", n_streams, state_stride,
+                    ps->N);
+    hipError_t e = launch_seed((const uint32_t *)d_params, d_states, (uint32_t)state_stride,
+                               (uint32_t)n_streams, (hipStream_t)stream);
+    return e == hipSuccess ? MTGP_OK : hip_fail(e, "seed kernel");
+}
+
 int mtgp_load_params(const mtgp_params *h_params, int n_streams, void *d_params, void *stream) {
     return upload_params(h_params, nullptr, n_streams, d_params, (hipStream_t)stream);
 }

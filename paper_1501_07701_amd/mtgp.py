@@ -65,6 +65,7 @@ _SIGS = {
     "mtgp_check_params": ([_VP, ctypes.c_int], ctypes.c_int),
     "mtgp_init_states": ([_VP, _VP, ctypes.c_int, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "mtgp_load_params": ([_VP, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_seed_states": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP], ctypes.c_int),
     "mtgp_release_params": ([_VP], ctypes.c_int),
     "mtgp_generate_u32": ([_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _VP, _VP],
                           ctypes.c_int),
@@ -175,6 +176,11 @@ def init_states(params: np.ndarray, seeds: np.ndarray, d_params, d_states, strid
         raise ValueError("one seed per stream")
     _check(lib().mtgp_init_states(_ptr(p), _ptr(s), p.shape[0], _ptr(d_params), _ptr(d_states),
                                   stride, _stream(stream)), "mtgp_init_states")
+
+
+def seed_states(d_params, d_states, stride: int, n_streams: int, stream=None) -> None:
+    _check(lib().mtgp_seed_states(_ptr(d_params), _ptr(d_states), stride, n_streams,
+                                  _stream(stream)), "mtgp_seed_states")
 
 
 def load_params(params: np.ndarray, d_params, stream=None) -> None:
@@ -291,6 +297,9 @@ class Generators:
                               device=self.device)
         generate(self.d_params, self.d_states, self.stride, n, count, out, dtype, stream)
         return out
+
+    def reseed(self, stream=None) -> None:
+        seed_states(self.d_params, self.d_states, self.stride, self.n, stream)
 
     def states_host(self) -> np.ndarray:
         return state_export(self.d_params, self.d_states, self.stride, self.n, self.N)
