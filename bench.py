@@ -87,11 +87,12 @@ def main():
     g = mtgp.Generators(params, seeds)
     out_u = torch.empty(n * count, dtype=torch.int32, device="cuda")
     out_f = torch.empty(n * count, dtype=torch.float32, device="cuda")
-    items_u = mtgp.make_work([(k, mtgp.U32, count, out_u.data_ptr() + 4 * k * count)
-                              for k in range(n)])
-    items_f = mtgp.make_work([(k, mtgp.F32, count, out_f.data_ptr() + 4 * k * count)
-                              for k in range(n)])
-    ws_u, ws_f = g.workspace(n), g.workspace(n)
+    list_u = [(k, mtgp.U32, count, out_u.data_ptr() + 4 * k * count) for k in range(n)]
+    list_f = [(k, mtgp.F32, count, out_f.data_ptr() + 4 * k * count) for k in range(n)]
+    items_u, items_f = mtgp.make_work(list_u), mtgp.make_work(list_f)
+    t_plan = time.perf_counter()
+    ws_u, ws_f = g.workspace(list_u), g.workspace(list_f)   # builds jump-ahead data once
+    t_plan = time.perf_counter() - t_plan
     stream = torch.cuda.current_stream()
 
     launch_ms = []
@@ -119,6 +120,10 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_per_step = elapsed * 1e3 / args.steps
+    seg_errors = mtgp.batch_errors(ws_u) + mtgp.batch_errors(ws_f)
+    if seg_errors:
+        log("jump-ahead segment checks failed: %d" % seg_errors)
+        sys.exit(3)
     avg_launch_ms = float(np.mean([a.elapsed_time(b) for a, b in launch_ms]))
 
     outputs_per_step = 2 * n * count
@@ -156,7 +161,9 @@ def main():
     W = N - params[:, 1].astype(np.int64)
     tun = mtgp.get_tuning(mexp)
     smax = tun.threads_per_stream * tun.outputs_per_lane
-    crit_steps = int(max(-(-count // min(int(w), smax)) for w in W))
+    # dependent steps of the slowest stream without jump-ahead
+    crit_steps = int(max(-(-count // min(int(w) if w < 64 else int(w) & ~31, smax))
+                         for w in W))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -185,7 +192,9 @@ def main():
         "data": "synthetic: seeded random MTGP32 parameter sets, seeds 1..128",
         "config": {"workload": cfg["name"], "mexp": mexp, "streams": n,
                    "outputs_per_stream": count, "passes": ["u32", "f32"],
-                   "tuning": list(tun.as_tuple())},
+                   "tuning": {"threads_per_stream": tun.threads_per_stream,
+                              "outputs_per_lane": tun.outputs_per_lane,
+                              "workgroup_size": tun.workgroup_size}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic},
@@ -193,8 +202,12 @@ def main():
         "hbm_write_frac_of_spec": round(value * 4 / HBM_PEAK_GBPS, 4),
         "avg_generate_launch_ms": round(avg_launch_ms, 3),
         "store_only_fill_GBps": round(fill_gbps, 1),
-        "critical_path_steps": crit_steps,
+        "unsplit_critical_path_steps": crit_steps,
         "min_step_width": int(W.min()),
+        "jump_ahead": {"target_steps": tun.jump_target_steps,
+                       "workspace_bytes": int(ws_u.numel()),
+                       "plan_build_s": round(t_plan, 3),
+                       "segment_check_failures": seg_errors},
     }
     print(json.dumps(line), flush=True)
 

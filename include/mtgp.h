@@ -131,18 +131,50 @@ typedef struct mtgp_work {
     void *d_out;
 } mtgp_work;
 
-/* Workspace bytes mtgp_generate_batch needs for n_items requests. */
+/* Smallest workspace mtgp_generate_batch accepts for n_items requests (no
+ * stream is split into jump-ahead segments with this much). */
 size_t mtgp_batch_workspace_bytes(int n_items);
+
+/* Workspace bytes that let this batch split every long stream into the
+ * jump-ahead segments the current tuning asks for.  May build the streams'
+ * jump-ahead data first (device work + host polynomial arithmetic, once per
+ * parameter set and stream), so it can synchronise the device. */
+int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items,
+                               int n_items, size_t *bytes);
 
 /* Batched generation: one persistent kernel advances many streams with
  * uneven lengths and mixed dtypes in a single launch, replayed from a
- * hipGraph captured once per (buffers, item count, tuning).  Items are
- * scheduled longest-critical-path first.  A stream id may appear at most
- * once per call.  d_workspace: mtgp_batch_workspace_bytes(n_items) bytes of
- * device memory the caller owns (work list + counters).  Asynchronous. */
+ * hipGraph captured once per (buffers, plan, tuning).  Items are scheduled
+ * longest-critical-path first.  A stream id may appear at most once per
+ * call.
+ *
+ * Jump-ahead (not in the paper; the generator's GF(2)-linearity makes it
+ * exact): a stream whose request needs more than the tuning's
+ * jump_target_steps dependent steps is cut into segments that run in
+ * parallel.  Their start states are XOR-combinations of the stream's first
+ * words given by x^(J-1) mod p, p an annihilating polynomial of the
+ * stream's word sequence found by Berlekamp-Massey and checked on the device
+ * (built once per stream, from its seed status).  Each segment checks its
+ * final state against the next segment's start; mismatches are counted in
+ * the workspace (mtgp_batch_errors).  Outputs are identical to unsplit
+ * generation.  Streams whose state was imported from elsewhere may fail the
+ * check: split batches then report errors and such streams should be run
+ * with jump_target_steps = 0.
+ *
+ * d_workspace: workspace_bytes (>= mtgp_batch_workspace_bytes(n_items)) of
+ * device memory the caller owns, 256-byte aligned; splitting is reduced to
+ * fit.  The library caches the uploaded plan in it: do not modify it between
+ * calls.  Asynchronous (the first call on a new parameter set may
+ * synchronise while it builds jump-ahead data). */
 int mtgp_generate_batch(const void *d_params, uint32_t *d_states,
                         int state_stride, const mtgp_work *h_items,
-                        int n_items, void *d_workspace, void *stream);
+                        int n_items, void *d_workspace, size_t workspace_bytes,
+                        void *stream);
+
+/* Synchronises `stream`, returns in *n the number of jump-ahead segment
+ * checks that failed in batches run on this workspace since the last call,
+ * and resets the count. */
+int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n);
 
 /* Launch tuning for one mexp: threads per stream (64 = one wave per stream,
  * several streams per workgroup; 256/512/1024 = one stream per workgroup),
@@ -151,6 +183,8 @@ typedef struct mtgp_tuning {
     int threads_per_stream;
     int outputs_per_lane;
     int workgroup_size;
+    int jump_target_steps;  /* split streams needing more dependent steps than
+                               this into jump-ahead segments; 0 = never */
 } mtgp_tuning;
 
 int mtgp_get_tuning(uint32_t mexp, mtgp_tuning *out);
@@ -158,17 +192,19 @@ int mtgp_set_tuning(uint32_t mexp, const mtgp_tuning *t);
 /* Number of candidate tunings compiled in for mexp, and candidate i. */
 int mtgp_tuning_candidates(uint32_t mexp, mtgp_tuning *out, int max_out);
 
-/* Autotuner: times every compiled candidate on the given batch (run on a
- * scratch copy of the states, so the caller's states are untouched), keeps
- * the fastest as the tuning for this mexp and returns it in *best.
- * d_scratch: n_streams * state_stride * 4 bytes + mtgp_batch_workspace_bytes
- * (n_items).  Output buffers named by the items are overwritten.
- * Synchronises `stream`.  h_ms (may be NULL) receives up to max_out
- * per-candidate times in ms, in mtgp_tuning_candidates order. */
+/* Autotuner: times every compiled launch candidate on the given batch (run
+ * on a scratch copy of the states, so the caller's states are untouched),
+ * then the jump-ahead target steps in {0, 1024, 4096, 16384, 65536} with the
+ * fastest candidate, keeps the fastest combination as the tuning for this
+ * mexp and returns it in *best.  d_scratch holds n_streams * state_stride * 4
+ * bytes (rounded up to 256) followed by the batch workspace;
+ * scratch_bytes is its size.  Output buffers named by the items are
+ * overwritten.  Synchronises `stream`.  h_ms (may be NULL) receives up to
+ * max_out per-candidate times in ms, in mtgp_tuning_candidates order. */
 int mtgp_autotune(const void *d_params, const uint32_t *d_states,
                   int state_stride, const mtgp_work *h_items, int n_items,
-                  void *d_scratch, int reps, void *stream, mtgp_tuning *best,
-                  float *h_ms, int max_out);
+                  void *d_scratch, size_t scratch_bytes, int reps, void *stream,
+                  mtgp_tuning *best, float *h_ms, int max_out);
 
 /* Checkpoint: copy n_streams state rows device -> host (h_out holds
  * n_streams * N words, densely packed) and back.  Synchronise `stream`.
@@ -200,6 +236,8 @@ typedef struct mtgp_server_opts {
     int max_queue;             /* pending requests before MTGP_EAGAIN      */
     uint64_t batch_window_ns;  /* wait this long for more requests when a
                                   launch slot is free but the queue is short */
+    uint64_t workspace_bytes_per_batch;  /* carved from the pool per launch
+                                  slot; bounds jump-ahead splitting */
 } mtgp_server_opts;
 
 enum { MTGP_PENDING = 0, MTGP_DONE = 1, MTGP_FAILED = 2 };

@@ -17,7 +17,11 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(BUILD, "libmtgp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mtgp_kernels.hip", "mtgp_api.cpp", "mtgp_server.cpp"]
+# HIP sources go through hipcc; mtgp_poly.cpp is plain host C++ built with
+# the host compiler and the carry-less multiply extension.
+SOURCES = ["mtgp_kernels.hip", "mtgp_api.cpp", "mtgp_batch.cpp", "mtgp_server.cpp"]
+HOST_SOURCES = ["mtgp_poly.cpp"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-mpclmul", "-I", CSRC]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-command-line-argument",
@@ -36,11 +40,21 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _compile_host(src: str) -> str:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = ["g++"] + HOST_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed for %s:\n%s%s" % (src, r.stdout, r.stderr))
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
-        objs = list(ex.map(_compile, srcs))
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + len(HOST_SOURCES)) as ex:
+        futs = [ex.submit(_compile, s) for s in SOURCES]
+        futs += [ex.submit(_compile_host, s) for s in HOST_SOURCES]
+        objs = [f.result() for f in futs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1,0 +1,875 @@
+// mtgp_batch.cpp -- batched generation: jump-ahead data per stream,
+// segment planning, workspace layout, uploads, hipGraph replay, autotuner.
+//
+// Jump-ahead.  For a stream with words x_0, x_1, ... (x_0..x_{N-1} its state
+// at the start of a call), the sequence x_1, x_2, ... lies in the orbit of
+// the GF(2)-linear state transition, so a polynomial p of degree D <= mexp
+// annihilates it: sum_i p_i x_{t+i} = 0 for all t >= 1 (word-wise XOR).
+// Then for g = x^J mod p, x_{t+J} = XOR_i g_i x_{t+i} for t >= 1, and the
+// state J+1 outputs ahead, x_{J+1} .. x_{J+N}, needs only x_1 .. x_{D+N}.
+// A split request therefore runs as
+//   A: a prefix item: the first P = D+1 outputs, also dumping x_0..x_{N+D};
+//   B: one jump item per later segment c: start state of output c*lseg,
+//      from g_c = x^(c*lseg - 1) mod p;
+//   C: every segment (the first one continues after the prefix), each
+//      checking its end state against the next segment's start state.
+// p is found once per stream from its seed status: Berlekamp-Massey on two
+// linear functionals of 2*mexp+127 words (lcm of the two), then checked on
+// the device over mexp further positions; if the check fails all 32 bit
+// functionals are used.  The orbit of a seeded state contains every later
+// state of that stream, so p stays valid as the stream advances or is
+// re-seeded.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "mtgp.h"
+#include "mtgp_host.hpp"
+#include "mtgp_internal.hpp"
+#include "mtgp_poly.hpp"
+
+namespace mtgp {
+
+struct StreamJump {
+    int status = 0;  // 1 usable, -1 never split this stream
+    int D = 0;       // degree of the annihilating polynomial p
+    std::unique_ptr<poly::Modulus> mod;
+    uint64_t lseg = 0;                       // segment length g is built for
+    poly::Poly xl;                           // x^lseg mod p
+    std::vector<std::vector<uint32_t>> g;    // g[c-1] = x^(c*lseg-1) mod p, packed
+    std::mutex mu;
+};
+
+Staging::~Staging() {
+    if (host) (void)hipHostFree(host);
+    if (done) (void)hipEventDestroy(done);
+}
+
+template <class F>
+static void parallel_for(int n, F f) {
+    int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
+    nt = std::min(nt, n);
+    if (nt <= 1) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (int i; (i = next.fetch_add(1)) < n;) f(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+static uint64_t pow2ceil(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+uint64_t step_outputs(uint32_t W, const mtgp_tuning &t) {
+    uint64_t s = W >= 64 ? (W & ~31u) : W;
+    const uint64_t smax = (uint64_t)t.threads_per_stream * (uint64_t)t.outputs_per_lane;
+    return std::max<uint64_t>(1, std::min(s, smax));
+}
+
+static std::vector<uint32_t> pack32(const poly::Poly &p, int nbits) {
+    std::vector<uint32_t> w((size_t)(nbits + 31) / 32, 0u);
+    for (size_t i = 0; i < w.size(); ++i) {
+        const uint64_t v = (i / 2 < p.size()) ? p[i / 2] : 0;
+        w[i] = (uint32_t)(v >> (32 * (i & 1)));
+    }
+    if (nbits & 31) w.back() &= (1u << (nbits & 31)) - 1u;
+    return w;
+}
+
+// lcm of the annihilators of the bit sequences parity(x_t & r), t >= 1.
+static poly::Poly annihilator(const uint32_t *x, int R, const std::vector<uint32_t> &funcs) {
+    std::vector<uint8_t> bits((size_t)R - 1);
+    poly::Poly acc;
+    for (uint32_t r : funcs) {
+        for (int t = 1; t < R; ++t) bits[(size_t)t - 1] = (uint8_t)__builtin_parity(x[t] & r);
+        poly::Poly p;
+        poly::berlekamp_massey(bits.data(), R - 1, &p);
+        acc = acc.empty() ? p : poly::lcm(acc, p);
+    }
+    return acc;
+}
+
+namespace {
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) { return hipMalloc(&p, std::max<size_t>(n, 256)); }
+};
+}  // namespace
+
+// Builds (once) the annihilating polynomial of every listed stream.
+static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_params,
+                        const std::vector<int> &streams, const mtgp_tuning &tun,
+                        hipStream_t s) {
+    std::lock_guard<std::mutex> lk(ps->jump_mu);
+    if (ps->jumps.size() != (size_t)ps->n) ps->jumps.assign((size_t)ps->n, nullptr);
+    std::vector<int> todo;
+    for (int k : streams)
+        if (!ps->jumps[k]) todo.push_back(k);
+    if (todo.empty()) return MTGP_OK;
+    std::sort(todo.begin(), todo.end());
+    todo.erase(std::unique(todo.begin(), todo.end()), todo.end());
+
+    const int N = ps->N;
+    const int mexp = (int)ps->mexp;
+    const int R = 2 * mexp + 128;            // raw words per stream (x_0 .. x_{R-1})
+    const int V = mexp + 64;                 // verification outputs per stream
+    const int PW = (mexp + 2 + 31) / 32 + 1; // packed words of p
+    const int chunk = 512;
+    hipError_t e;
+    DevBuf d_seeded;
+    if ((e = d_seeded.alloc((size_t)ps->n * N * 4)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = launch_seed((const uint32_t *)d_params, (uint32_t *)d_seeded.p, (uint32_t)N,
+                         (uint32_t)ps->n, s)) != hipSuccess)
+        return hip_fail(e, "seed kernel");
+    const int cn = std::min<int>(chunk, (int)todo.size());
+    DevBuf d_raw, d_out, d_items, d_counter, d_jitems, d_poly, d_vout;
+    if ((e = d_raw.alloc((size_t)cn * R * 4)) != hipSuccess ||
+        (e = d_out.alloc((size_t)cn * (R - N) * 4)) != hipSuccess ||
+        (e = d_items.alloc((size_t)cn * sizeof(BatchItem))) != hipSuccess ||
+        (e = d_counter.alloc(256)) != hipSuccess ||
+        (e = d_jitems.alloc((size_t)cn * sizeof(JumpItem))) != hipSuccess ||
+        (e = d_poly.alloc((size_t)cn * PW * 4)) != hipSuccess ||
+        (e = d_vout.alloc((size_t)cn * V * 4)) != hipSuccess)
+        return hip_fail(e, "hipMalloc(jump planning)");
+    std::vector<uint32_t> raw((size_t)cn * R), vout((size_t)cn * V);
+
+    for (size_t c0 = 0; c0 < todo.size(); c0 += chunk) {
+        const int m = (int)std::min<size_t>(chunk, todo.size() - c0);
+        std::vector<BatchItem> items((size_t)m);
+        for (int j = 0; j < m; ++j) {
+            const int k = todo[c0 + j];
+            BatchItem &b = items[j];
+            std::memset(&b, 0, sizeof b);
+            b.stream = (uint32_t)k;
+            b.mode = MODE_RAW;
+            b.count = (uint64_t)(R - N);
+            b.out = (uint64_t)(uintptr_t)((uint32_t *)d_out.p + (size_t)j * (R - N));
+            b.state_in = (uint64_t)(uintptr_t)((uint32_t *)d_seeded.p + (size_t)k * N);
+            b.raw = (uint64_t)(uintptr_t)((uint32_t *)d_raw.p + (size_t)j * R);
+        }
+        if ((e = hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(BatchItem),
+                                hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(plan items)");
+        LaunchArgs a{};
+        a.params = (const uint32_t *)d_params;
+        a.items = (const BatchItem *)d_items.p;
+        a.n_items = (uint32_t)m;
+        a.counter = (uint32_t *)d_counter.p;
+        a.err = (uint32_t *)d_counter.p + 1;
+        a.persistent = true;
+        a.num_cus = device_cus();
+        a.stream = s;
+        if ((e = launch_reset((uint32_t *)d_counter.p, s)) != hipSuccess)
+            return hip_fail(e, "reset kernel");
+        int rc = launch_tuned(N, tun, a);
+        if (rc) return rc;
+        if ((e = hipMemcpyAsync(raw.data(), d_raw.p, (size_t)m * R * 4, hipMemcpyDeviceToHost,
+                                s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_fail(e, "raw words to host");
+
+        std::vector<poly::Poly> P((size_t)m);
+        std::vector<uint8_t> ok((size_t)m, 0);
+        const std::vector<uint32_t> quick = {0xFFFFFFFFu, 0x6A09E667u};
+        std::vector<uint32_t> all = quick;
+        for (int b = 0; b < 32; ++b) all.push_back(1u << b);
+        for (int pass = 0; pass < 2; ++pass) {
+            parallel_for(m, [&](int j) {
+                if (ok[j]) return;
+                P[j] = annihilator(&raw[(size_t)j * R], R, pass == 0 ? quick : all);
+            });
+            // device check: y_t = sum_i p_i x_{t+i} must vanish for t = 1..D
+            std::vector<JumpItem> jit((size_t)m);
+            std::vector<uint32_t> pw((size_t)m * PW, 0u);
+            int nj = 0;
+            std::vector<int> which;
+            for (int j = 0; j < m; ++j) {
+                if (ok[j]) continue;
+                const int D = poly::degree(P[j]);
+                if (D < 1 || D > mexp) continue;
+                const std::vector<uint32_t> w = pack32(P[j], D + 1);
+                std::memcpy(&pw[(size_t)nj * PW], w.data(), w.size() * 4);
+                JumpItem &ji = jit[nj];
+                ji.raw = (uint64_t)(uintptr_t)((uint32_t *)d_raw.p + (size_t)j * R);
+                ji.poly = (uint64_t)(uintptr_t)((uint32_t *)d_poly.p + (size_t)nj * PW);
+                ji.out = (uint64_t)(uintptr_t)((uint32_t *)d_vout.p + (size_t)nj * V);
+                ji.nbits = (uint32_t)(D + 1);
+                ji.m = (uint32_t)mexp;
+                which.push_back(j);
+                ++nj;
+            }
+            if (nj == 0) break;
+            if ((e = hipMemcpyAsync(d_poly.p, pw.data(), (size_t)nj * PW * 4,
+                                    hipMemcpyHostToDevice, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(d_jitems.p, jit.data(), (size_t)nj * sizeof(JumpItem),
+                                    hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "hipMemcpyAsync(check items)");
+            if ((e = launch_jump((const JumpItem *)d_jitems.p, (uint32_t)nj, device_cus(), s)) !=
+                hipSuccess)
+                return hip_fail(e, "jump kernel (check)");
+            if ((e = hipMemcpyAsync(vout.data(), d_vout.p, (size_t)nj * V * 4,
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return hip_fail(e, "check results to host");
+            // y has order <= mexp (it lies in the same orbit), so mexp
+            // consecutive zeros mean y vanishes for every t >= 1
+            for (int q = 0; q < nj; ++q) {
+                const int j = which[q];
+                bool zero = true;
+                for (int t = 0; t < mexp && zero; ++t) zero = vout[(size_t)q * V + t] == 0u;
+                ok[j] = zero ? 1 : 0;
+            }
+        }
+        std::vector<std::shared_ptr<StreamJump>> built((size_t)m);
+        parallel_for(m, [&](int j) {
+            auto sj = std::make_shared<StreamJump>();
+            if (ok[j]) {
+                sj->status = 1;
+                sj->D = poly::degree(P[j]);
+                sj->mod = std::make_unique<poly::Modulus>(P[j]);
+            } else {
+                sj->status = -1;
+            }
+            built[j] = sj;
+        });
+        for (int j = 0; j < m; ++j) ps->jumps[todo[c0 + j]] = built[j];
+    }
+    return MTGP_OK;
+}
+
+// g[c-1] = x^(c*lseg-1) mod p for c = 1 .. cmax-1.
+static void ensure_g(StreamJump &sj, uint64_t lseg, int cmax) {
+    std::lock_guard<std::mutex> lk(sj.mu);
+    if (sj.lseg != lseg) {
+        sj.lseg = lseg;
+        sj.g.clear();
+        sj.xl = sj.mod->powx(lseg);
+    }
+    if ((int)sj.g.size() >= cmax - 1) return;
+    poly::Poly cur;
+    if (sj.g.empty()) {
+        cur = sj.mod->powx(lseg - 1);
+        sj.g.push_back(pack32(cur, sj.D));
+    } else {
+        // unpack the last one
+        const std::vector<uint32_t> &w = sj.g.back();
+        cur.assign((w.size() + 1) / 2, 0);
+        for (size_t i = 0; i < w.size(); ++i) cur[i / 2] |= (uint64_t)w[i] << (32 * (i & 1));
+        poly::trim(cur);
+    }
+    while ((int)sj.g.size() < cmax - 1) {
+        cur = sj.mod->mulmod(cur, sj.xl);
+        sj.g.push_back(pack32(cur, sj.D));
+    }
+}
+
+// ---------------------------------------------------------------- plan ----
+
+namespace {
+struct Seg {
+    int req;
+    int C = 1;           // segments (1 = not split)
+    uint64_t lseg = 0;
+    StreamJump *sj = nullptr;
+};
+
+struct Layout {
+    size_t off_A = 0, off_B = 0, off_C = 0, off_cd = 0, off_poly = 0, up_end = 0;
+    size_t off_raw = 0, off_js = 0, total = 0;
+};
+
+size_t al256(size_t v) { return (v + 255) / 256 * 256; }
+}  // namespace
+
+size_t batch_min_ws_bytes(int n_items) {
+    // header + A/B (none) + C items + countdowns
+    return 256 + al256((size_t)std::max(n_items, 0) * sizeof(BatchItem)) +
+           al256((size_t)std::max(n_items, 0) * 4);
+}
+
+static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_t n_req) {
+    size_t nA = 0, nB = 0, nC = 0, poly_words = 0, raw_words = 0, js_words = 0;
+    for (const Seg &g : segs) {
+        if (g.C <= 1) {
+            ++nC;
+            continue;
+        }
+        ++nA;
+        nB += (size_t)g.C - 1;
+        nC += (size_t)g.C;
+        poly_words += ((size_t)g.C - 1) * (((size_t)g.sj->D + 31) / 32);
+        raw_words += ((size_t)ps.N + (size_t)g.sj->D + 1 + 63) / 64 * 64;
+        js_words += (size_t)g.C * (size_t)ps.N;
+    }
+    Layout L;
+    L.off_A = 256;
+    L.off_B = L.off_A + al256(nA * sizeof(BatchItem));
+    L.off_C = L.off_B + al256(nB * sizeof(JumpItem));
+    L.off_cd = L.off_C + al256(nC * sizeof(BatchItem));
+    L.off_poly = L.off_cd + al256(n_req * 4);
+    L.up_end = L.off_poly + al256(poly_words * 4);
+    L.off_raw = L.up_end;
+    L.off_js = L.off_raw + al256(raw_words * 4);
+    L.total = L.off_js + al256(js_words * 4);
+    return L;
+}
+
+static int upload(Staging &st, const uint8_t *src, size_t n, void *d_dst, hipStream_t s) {
+    if (st.pending) {
+        hipError_t e = hipEventSynchronize(st.done);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
+        st.pending = false;
+    }
+    if (n > st.cap) {
+        if (st.host) (void)hipHostFree(st.host);
+        st.host = nullptr;
+        const size_t cap = std::max<size_t>(n, 1 << 16);
+        hipError_t e = hipHostMalloc((void **)&st.host, cap, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            st.cap = 0;
+            return hip_fail(e, "hipHostMalloc(staging)");
+        }
+        st.cap = cap;
+    }
+    if (!st.done) {
+        hipError_t e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    if (n == 0) return MTGP_OK;
+    std::memcpy(st.host, src, n);
+    hipError_t e = hipMemcpyAsync(d_dst, st.host, n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(work list)");
+    e = hipEventRecord(st.done, s);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    st.pending = true;
+    return MTGP_OK;
+}
+
+// What was last uploaded to a workspace, so identical calls replay at once.
+namespace {
+struct WsRecord {
+    uint64_t sig = 0;
+    uint32_t nA = 0, nB = 0, nC = 0;
+};
+std::mutex g_ws_mu;
+std::map<const void *, WsRecord> g_ws;
+
+uint64_t mix(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+struct GraphKey {
+    const void *ws;
+    uint32_t nA, nB, nC;
+    const void *params;
+    int N, tps, k, wg, device;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, device) <
+               std::tie(o.ws, o.nA, o.nB, o.nC, o.params, o.N, o.tps, o.k, o.wg, o.device);
+    }
+};
+std::mutex g_graph_mu;
+std::map<GraphKey, hipGraphExec_t> g_graphs;
+std::map<int, hipStream_t> g_capture_streams;
+
+bool graphs_enabled() {
+    const char *v = getenv("MTGP_GRAPH");
+    return !(v && v[0] == '0');
+}
+}  // namespace
+
+// Launches the three phases of a planned batch on `s`.
+static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, uint32_t nA,
+                         uint32_t nB, uint32_t nC, const Layout &L, const mtgp_tuning &t,
+                         hipStream_t s) {
+    uint32_t *hdr = (uint32_t *)ws;
+    LaunchArgs a{};
+    a.params = (const uint32_t *)d_params;
+    a.err = hdr + 2;
+    a.persistent = true;
+    a.num_cus = device_cus();
+    a.stream = s;
+    hipError_t e;
+    if (nA) {
+        if ((e = launch_reset(hdr + 0, s)) != hipSuccess) return hip_fail(e, "reset kernel");
+        a.items = (const BatchItem *)(ws + L.off_A);
+        a.n_items = nA;
+        a.counter = hdr + 0;
+        int rc = launch_tuned(ps.N, t, a);
+        if (rc) return rc;
+    }
+    if (nB) {
+        if ((e = launch_jump((const JumpItem *)(ws + L.off_B), nB, device_cus(), s)) !=
+            hipSuccess)
+            return hip_fail(e, "jump kernel");
+    }
+    if ((e = launch_reset(hdr + 1, s)) != hipSuccess) return hip_fail(e, "reset kernel");
+    a.items = (const BatchItem *)(ws + L.off_C);
+    a.n_items = nC;
+    a.counter = hdr + 1;
+    return launch_tuned(ps.N, t, a);
+}
+
+int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
+              int stride, const std::vector<Request> &reqs, void *d_ws, size_t ws_bytes,
+              hipStream_t s, const mtgp_tuning &t, bool use_graph, Staging &stage) {
+    if (reqs.empty()) return MTGP_OK;
+    bool has_flags = false;
+    uint64_t sig = mix(0x51ull, (uint64_t)(uintptr_t)d_params);
+    sig = mix(sig, ps->generation);
+    sig = mix(sig, (uint64_t)(uintptr_t)d_states);
+    sig = mix(sig, (uint64_t)stride);
+    sig = mix(sig, ws_bytes);
+    sig = mix(sig, ((uint64_t)t.threads_per_stream << 48) ^ ((uint64_t)t.outputs_per_lane << 32) ^
+                       ((uint64_t)t.workgroup_size << 16) ^ (uint64_t)(uint32_t)t.jump_target_steps);
+    for (const Request &r : reqs) {
+        sig = mix(sig, ((uint64_t)(uint32_t)r.stream << 32) | r.dtype);
+        sig = mix(sig, r.count);
+        sig = mix(sig, (uint64_t)(uintptr_t)r.d_out);
+        has_flags |= r.flag != 0;
+    }
+    char *ws = (char *)d_ws;
+    Layout L;
+    uint32_t nA = 0, nB = 0, nC = 0;
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        auto it = g_ws.find(d_ws);
+        if (!has_flags && it != g_ws.end() && it->second.sig == sig) {
+            cached = true;
+            nA = it->second.nA;
+            nB = it->second.nB;
+            nC = it->second.nC;
+        }
+    }
+    std::vector<Seg> segs(reqs.size());
+    if (!cached) {
+        // which requests want splitting at the tuning's target
+        const int N = ps->N;
+        const uint64_t minseg = pow2ceil((uint64_t)ps->mexp + 128);
+        std::vector<int> want;
+        uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            segs[i].req = (int)i;
+            const uint64_t so = step_outputs(ps->W[reqs[i].stream], t);
+            if (T && reqs[i].count > 2 * minseg && (reqs[i].count + so - 1) / so > T)
+                want.push_back(reqs[i].stream);
+        }
+        if (!want.empty()) {
+            int rc = ensure_jumps(ps, d_params, want, t, s);
+            if (rc) return rc;
+        }
+        // snapshot of the streams' jump data (entries are built once and
+        // never replaced while the parameter set lives)
+        std::vector<StreamJump *> sjs(reqs.size(), nullptr);
+        {
+            std::lock_guard<std::mutex> lk(ps->jump_mu);
+            if (ps->jumps.size() == (size_t)ps->n)
+                for (size_t i = 0; i < reqs.size(); ++i) sjs[i] = ps->jumps[reqs[i].stream].get();
+        }
+        // plan, doubling the target until the workspace fits
+        while (true) {
+            for (size_t i = 0; i < reqs.size(); ++i) {
+                Seg &g = segs[i];
+                g.C = 1;
+                g.sj = nullptr;
+                if (!T) continue;
+                const Request &r = reqs[i];
+                const uint64_t so = step_outputs(ps->W[r.stream], t);
+                if (r.count <= 2 * minseg || (r.count + so - 1) / so <= T) continue;
+                StreamJump *sj = sjs[i];
+                if (!sj || sj->status != 1) continue;
+                const uint64_t lseg = std::max(minseg, pow2ceil(T * so));
+                const uint64_t C = (r.count + lseg - 1) / lseg;
+                if (C < 2) continue;
+                g.C = (int)C;
+                g.lseg = lseg;
+                g.sj = sj;
+            }
+            L = layout_for(*ps, segs, reqs.size());
+            if (L.total <= ws_bytes || !T) break;
+            T *= 2;
+            if (T > (1ull << 40)) T = 0;
+        }
+        if (L.total > ws_bytes)
+            return fail(MTGP_EINVAL, "workspace of %zu bytes too small (need %zu)", ws_bytes,
+                        L.total);
+        // polynomials
+        std::vector<Seg *> split;
+        for (Seg &g : segs)
+            if (g.C > 1) split.push_back(&g);
+        parallel_for((int)split.size(), [&](int i) { ensure_g(*split[i]->sj, split[i]->lseg, split[i]->C); });
+
+        // build the uploaded image [0, up_end): a zeroed header (claim
+        // counters, error count), the item tables, countdowns, polynomials
+        std::vector<uint8_t> img(L.up_end, 0);
+        auto at = [&](size_t off) { return img.data() + off; };
+        std::vector<std::pair<uint64_t, BatchItem>> A, C;
+        std::vector<JumpItem> B;
+        size_t raw_off = L.off_raw, js_off = L.off_js, poly_off = L.off_poly;
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            const Request &r = reqs[i];
+            const Seg &g = segs[i];
+            const uint32_t mode = r.dtype == MTGP_F32 ? MODE_F32 : 0u;
+            uint32_t *row = d_states + (size_t)r.stream * stride;
+            const uint64_t so = step_outputs(ps->W[r.stream], t);
+            uint32_t *cd = (uint32_t *)(ws + L.off_cd) + i;
+            auto base_item = [&](uint64_t count, uint64_t out_off) {
+                BatchItem b;
+                std::memset(&b, 0, sizeof b);
+                b.stream = (uint32_t)r.stream;
+                b.mode = mode;
+                b.count = count;
+                b.out = (uint64_t)(uintptr_t)((char *)r.d_out + out_off * 4);
+                b.flag = r.flag;
+                b.countdown = r.flag ? (uint64_t)(uintptr_t)cd : 0;
+                return b;
+            };
+            if (g.C <= 1) {
+                BatchItem b = base_item(r.count, 0);
+                b.state_in = b.state_out = (uint64_t)(uintptr_t)row;
+                C.emplace_back((r.count + so - 1) / so, b);
+                ((uint32_t *)at(L.off_cd))[i] = 1;
+                continue;
+            }
+            const int D = g.sj->D;
+            const uint64_t P = (uint64_t)D + 1;
+            uint32_t *raw = (uint32_t *)(ws + raw_off);
+            raw_off += ((size_t)N + (size_t)D + 1 + 63) / 64 * 64 * 4;
+            uint32_t *js = (uint32_t *)(ws + js_off);  // C states of N words
+            js_off += (size_t)g.C * N * 4;
+            // A: prefix
+            BatchItem a = base_item(P, 0);
+            a.mode |= MODE_RAW;
+            a.state_in = (uint64_t)(uintptr_t)row;
+            a.state_out = (uint64_t)(uintptr_t)js;
+            a.raw = (uint64_t)(uintptr_t)raw;
+            a.flag = a.countdown = 0;
+            A.emplace_back((P + so - 1) / so, a);
+            // B: jumps
+            const size_t pw = ((size_t)D + 31) / 32;
+            for (int c = 1; c < g.C; ++c) {
+                JumpItem j;
+                j.raw = (uint64_t)(uintptr_t)raw;
+                j.poly = (uint64_t)(uintptr_t)(ws + poly_off);
+                j.out = (uint64_t)(uintptr_t)(js + (size_t)c * N);
+                j.nbits = (uint32_t)D;
+                j.m = (uint32_t)N;
+                std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
+                poly_off += pw * 4;
+                B.push_back(j);
+            }
+            // C: segments
+            for (int c = 0; c < g.C; ++c) {
+                const uint64_t beg = (uint64_t)c * g.lseg;
+                const uint64_t end = std::min<uint64_t>(r.count, beg + g.lseg);
+                const uint64_t start = c == 0 ? P : beg;
+                BatchItem b = base_item(end - start, start);
+                b.state_in = (uint64_t)(uintptr_t)(js + (size_t)c * N);
+                if (c + 1 < g.C) {
+                    b.mode |= MODE_VERIFY;
+                    b.verify = (uint64_t)(uintptr_t)(js + (size_t)(c + 1) * N);
+                } else {
+                    b.state_out = (uint64_t)(uintptr_t)row;
+                }
+                C.emplace_back((end - start + so - 1) / so, b);
+            }
+            ((uint32_t *)at(L.off_cd))[i] = (uint32_t)g.C;
+        }
+        auto lpt = [](const auto &x, const auto &y) { return x.first > y.first; };
+        std::stable_sort(A.begin(), A.end(), lpt);
+        std::stable_sort(C.begin(), C.end(), lpt);
+        for (size_t i = 0; i < A.size(); ++i)
+            std::memcpy(at(L.off_A) + i * sizeof(BatchItem), &A[i].second, sizeof(BatchItem));
+        if (!B.empty()) std::memcpy(at(L.off_B), B.data(), B.size() * sizeof(JumpItem));
+        for (size_t i = 0; i < C.size(); ++i)
+            std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].second, sizeof(BatchItem));
+        nA = (uint32_t)A.size();
+        nB = (uint32_t)B.size();
+        nC = (uint32_t)C.size();
+        int rc = upload(stage, img.data(), img.size(), ws, s);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        g_ws[d_ws] = WsRecord{has_flags ? 0 : sig, nA, nB, nC};
+    } else {
+        L = layout_for(*ps, std::vector<Seg>(), 0);  // only the fixed offsets are used below
+        // recover the item-table offsets from the recorded counts
+        L.off_A = 256;
+        L.off_B = L.off_A + al256((size_t)nA * sizeof(BatchItem));
+        L.off_C = L.off_B + al256((size_t)nB * sizeof(JumpItem));
+    }
+
+    if (!use_graph || !graphs_enabled())
+        return launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, s);
+
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    GraphKey key{d_ws, nA, nB, nC, d_params, ps->N, t.threads_per_stream, t.outputs_per_lane,
+                 t.workgroup_size, dev};
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        hipStream_t cs;
+        auto cit = g_capture_streams.find(dev);
+        if (cit == g_capture_streams.end()) {
+            hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+            g_capture_streams[dev] = cs;
+        } else {
+            cs = cit->second;
+        }
+        if (g_graphs.size() >= 256) {
+            for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
+            g_graphs.clear();
+        }
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        int rc = launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, cs);
+        hipGraph_t gr = nullptr;
+        e = hipStreamEndCapture(cs, &gr);
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = g_graphs.emplace(key, ge).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return MTGP_OK;
+}
+
+int validate_requests(const ParamSet &ps, const mtgp_work *items, int n) {
+    if (n < 0 || (n > 0 && !items)) return fail(MTGP_EINVAL, "bad item list (n=%d)", n);
+    std::vector<uint8_t> seen((size_t)ps.n, 0);
+    for (int i = 0; i < n; ++i) {
+        const mtgp_work &w = items[i];
+        if (w.stream_id < 0 || w.stream_id >= ps.n)
+            return fail(MTGP_EINVAL, "item %d: stream %d outside [0, %d)", i, w.stream_id, ps.n);
+        if (seen[w.stream_id]++)
+            return fail(MTGP_EINVAL, "item %d: stream %d appears twice in one batch", i,
+                        w.stream_id);
+        if (w.dtype != MTGP_U32 && w.dtype != MTGP_F32)
+            return fail(MTGP_EINVAL, "item %d: dtype %u", i, w.dtype);
+        if (w.count > 0 && !w.d_out) return fail(MTGP_EINVAL, "item %d: d_out is NULL", i);
+        if (((uintptr_t)w.d_out & 3u) != 0)
+            return fail(MTGP_EINVAL, "item %d: d_out not 4-byte aligned", i);
+    }
+    return MTGP_OK;
+}
+
+static std::vector<Request> to_requests(const mtgp_work *items, int n) {
+    std::vector<Request> r;
+    r.reserve((size_t)n);
+    for (int i = 0; i < n; ++i)
+        if (items[i].count > 0)
+            r.push_back(Request{items[i].stream_id, items[i].dtype, items[i].count,
+                                items[i].d_out, 0});
+    return r;
+}
+
+static Staging g_stage;
+
+static int batch_common(const void *d_params, uint32_t *d_states, int stride,
+                        const mtgp_work *h_items, int n_items, void *d_ws, size_t ws_bytes,
+                        hipStream_t s, const mtgp_tuning *force, bool use_graph,
+                        Staging &stage) {
+    auto ps = lookup_params(d_params, 0);
+    if (!ps) return MTGP_EINVAL;
+    if (!d_states || stride < ps->N)
+        return fail(MTGP_EINVAL, "state_stride %d < N=%d or NULL states", stride, ps->N);
+    if (!d_ws || ((uintptr_t)d_ws & 255u))
+        return fail(MTGP_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    int rc = validate_requests(*ps, h_items, n_items);
+    if (rc) return rc;
+    if (ws_bytes < batch_min_ws_bytes(n_items))
+        return fail(MTGP_EINVAL, "workspace of %zu bytes below the minimum %zu", ws_bytes,
+                    batch_min_ws_bytes(n_items));
+    const mtgp_tuning t = force ? *force : tuning_for(ps->N);
+    std::lock_guard<std::mutex> lk(stage.mu);
+    return run_batch(ps, d_params, d_states, stride, to_requests(h_items, n_items), d_ws,
+                     ws_bytes, s, t, use_graph, stage);
+}
+
+}  // namespace mtgp
+
+using namespace mtgp;
+
+extern "C" {
+
+size_t mtgp_batch_workspace_bytes(int n_items) { return batch_min_ws_bytes(n_items); }
+
+int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items, int n_items,
+                               size_t *bytes) {
+    if (!bytes) return fail(MTGP_EINVAL, "bytes is NULL");
+    auto ps = lookup_params(d_params, 0);
+    if (!ps) return MTGP_EINVAL;
+    int rc = validate_requests(*ps, h_items, n_items);
+    if (rc) return rc;
+    const mtgp_tuning t = tuning_for(ps->N);
+    const uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
+    const uint64_t minseg = pow2ceil((uint64_t)ps->mexp + 128);
+    std::vector<int> want;
+    std::vector<Request> reqs = to_requests(h_items, n_items);
+    for (const Request &r : reqs) {
+        const uint64_t so = step_outputs(ps->W[r.stream], t);
+        if (T && r.count > 2 * minseg && (r.count + so - 1) / so > T) want.push_back(r.stream);
+    }
+    if (!want.empty()) {
+        rc = ensure_jumps(ps, d_params, want, t, nullptr);
+        if (rc) return rc;
+    }
+    std::vector<Seg> segs(reqs.size());
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        segs[i].req = (int)i;
+        const uint64_t so = step_outputs(ps->W[r.stream], t);
+        if (!T || r.count <= 2 * minseg || (r.count + so - 1) / so <= T) continue;
+        StreamJump *sj = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(ps->jump_mu);
+            if (ps->jumps.size() == (size_t)ps->n) sj = ps->jumps[r.stream].get();
+        }
+        if (!sj || sj->status != 1) continue;
+        const uint64_t lseg = std::max(minseg, pow2ceil(T * so));
+        const uint64_t C = (r.count + lseg - 1) / lseg;
+        if (C < 2) continue;
+        segs[i].C = (int)C;
+        segs[i].lseg = lseg;
+        segs[i].sj = sj;
+    }
+    *bytes = std::max(layout_for(*ps, segs, reqs.size()).total, batch_min_ws_bytes(n_items));
+    return MTGP_OK;
+}
+
+int mtgp_generate_batch(const void *d_params, uint32_t *d_states, int state_stride,
+                        const mtgp_work *h_items, int n_items, void *d_workspace,
+                        size_t workspace_bytes, void *stream) {
+    return batch_common(d_params, d_states, state_stride, h_items, n_items, d_workspace,
+                        workspace_bytes, (hipStream_t)stream, nullptr, true, g_stage);
+}
+
+int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n) {
+    if (!d_workspace || !n) return fail(MTGP_EINVAL, "NULL workspace or n");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, (uint32_t *)d_workspace + 2, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "read error count");
+    *n = v;
+    const uint32_t zero = 0;
+    e = hipMemcpyAsync((uint32_t *)d_workspace + 2, &zero, 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? MTGP_OK : hip_fail(e, "reset error count");
+}
+
+int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stride,
+                  const mtgp_work *h_items, int n_items, void *d_scratch, size_t scratch_bytes,
+                  int reps, void *stream, mtgp_tuning *best, float *h_ms, int max_out) {
+    auto ps = lookup_params(d_params, 0);
+    if (!ps) return MTGP_EINVAL;
+    if (!d_scratch || ((uintptr_t)d_scratch & 255u))
+        return fail(MTGP_EINVAL, "scratch must be non-NULL and 256-byte aligned");
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t state_bytes = (size_t)ps->n * (size_t)state_stride * 4;
+    const size_t state_al = (state_bytes + 255) / 256 * 256;
+    if (scratch_bytes < state_al + batch_min_ws_bytes(n_items))
+        return fail(MTGP_EINVAL, "scratch of %zu bytes too small", scratch_bytes);
+    uint32_t *scratch_states = (uint32_t *)d_scratch;
+    void *ws = (char *)d_scratch + state_al;
+    const size_t ws_bytes = scratch_bytes - state_al;
+    hipError_t e = hipMemcpyAsync(scratch_states, d_states, state_bytes,
+                                  hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(scratch states)");
+    mtgp_tuning cands[64];
+    const int nc = std::min(64, mtgp_tuning_candidates(ps->mexp, cands, 64));
+    const mtgp_tuning cur = tuning_for(ps->N);
+    hipEvent_t ev0, ev1;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    Staging stage;
+    auto time_one = [&](const mtgp_tuning &t, float *ms) -> int {
+        int rc = batch_common(d_params, scratch_states, state_stride, h_items, n_items, ws,
+                              ws_bytes, s, &t, false, stage);  // warm-up + planning
+        if (rc) return rc;
+        float total = 0.f;
+        for (int r = 0; r < reps; ++r) {
+            (void)hipEventRecord(ev0, s);
+            rc = batch_common(d_params, scratch_states, state_stride, h_items, n_items, ws,
+                              ws_bytes, s, &t, false, stage);
+            (void)hipEventRecord(ev1, s);
+            if (rc) return rc;
+            hipError_t e2 = hipEventSynchronize(ev1);
+            if (e2 != hipSuccess) return hip_fail(e2, "hipEventSynchronize(autotune)");
+            float m = 0.f;
+            (void)hipEventElapsedTime(&m, ev0, ev1);
+            total += m;
+        }
+        *ms = total / (float)reps;
+        return MTGP_OK;
+    };
+    float best_ms = 1e30f;
+    mtgp_tuning bt = cur;
+    int rc = MTGP_OK;
+    for (int i = 0; i < nc && rc == MTGP_OK; ++i) {
+        cands[i].jump_target_steps = cur.jump_target_steps;
+        float ms = 0.f;
+        rc = time_one(cands[i], &ms);
+        if (rc) break;
+        if (h_ms && i < max_out) h_ms[i] = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            bt = cands[i];
+        }
+    }
+    const int targets[] = {0, 1024, 4096, 16384, 65536};
+    for (int T : targets) {
+        if (rc) break;
+        if (T == bt.jump_target_steps) continue;
+        mtgp_tuning t = bt;
+        t.jump_target_steps = T;
+        float ms = 0.f;
+        rc = time_one(t, &ms);
+        if (rc == MTGP_OK && ms < best_ms) {
+            best_ms = ms;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rc) return rc;
+    rc = mtgp_set_tuning(ps->mexp, &bt);
+    if (rc) return rc;
+    if (best) *best = bt;
+    return MTGP_OK;
+}
+
+}  // extern "C"

@@ -23,27 +23,54 @@ enum : uint32_t {
     P_WORDS = 64,
 };
 
-// Device work-list entry (32 bytes).
+// BatchItem.mode bits
+enum : uint32_t {
+    MODE_F32 = 1u,     // float32 output (else uint32)
+    MODE_RAW = 2u,     // also store the raw words x_0 .. x_{N+count-1} at raw
+    MODE_VERIFY = 4u,  // compare the end state with verify[0..N), count mismatches
+};
+
+// Device work-list entry (80 bytes): advance a stream from state_in by
+// `count` outputs written to `out`, store the end state at state_out.
 struct BatchItem {
     uint32_t stream;
-    uint32_t dtype;  // 0 uint32, 1 float32
+    uint32_t mode;
     uint64_t count;
-    uint64_t out;    // device address
-    uint64_t flag;   // 0, or a host-mapped uint32 set to 1 when the item is done
+    uint64_t out;        // device address of the outputs
+    uint64_t state_in;   // N words
+    uint64_t state_out;  // N words, or 0
+    uint64_t raw;        // MODE_RAW destination
+    uint64_t verify;     // MODE_VERIFY reference state
+    uint64_t flag;       // 0, or a host-mapped uint32 set to 1 when the request is done
+    uint64_t countdown;  // 0, or a device uint32 of segments still running for
+                         // this request: the segment that ends it raises `flag`
+    uint64_t reserved;
 };
-static_assert(sizeof(BatchItem) == 32, "BatchItem layout");
+static_assert(sizeof(BatchItem) == 80, "BatchItem layout");
+
+// Jump evaluation item (32 bytes): out[m] = XOR_{i < nbits, g_i = 1}
+// raw[1 + i + m] for m < m_count.
+struct JumpItem {
+    uint64_t raw;     // words x_0, x_1, ... of a stream
+    uint64_t poly;    // coefficients g_0 .. g_{nbits-1}, 32 per uint32 word
+    uint64_t out;     // m words
+    uint32_t nbits;
+    uint32_t m;
+};
+static_assert(sizeof(JumpItem) == 32, "JumpItem layout");
 
 struct LaunchArgs {
     const uint32_t *params;
-    uint32_t *states;
-    uint32_t stride;
-    const BatchItem *items;  // nullptr: plain mode
+    const BatchItem *items;  // nullptr: plain mode, item i is stream i
     uint32_t n_items;
-    uint32_t *counter;
+    uint32_t *plain_states;  // plain mode: state rows, outputs, count, dtype
+    uint32_t plain_stride;
     uint32_t *plain_out;
     uint64_t plain_count;
-    uint32_t plain_f32;
-    int grid;      // <= 0: persistent (occupancy x CUs)
+    uint32_t plain_mode;
+    uint32_t *counter;
+    uint32_t *err;
+    bool persistent;
     int num_cus;
     void *stream;
 };
@@ -56,6 +83,7 @@ struct VariantInfo {
 int variant_count(int n_words, VariantInfo *out, int max_out);
 hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs &a,
                           bool *found);
+hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s);
 hipError_t launch_reset(uint32_t *counter, hipStream_t s);

@@ -7,13 +7,21 @@
 // and in device memory between launches.
 //
 // Step structure.  With W = N - pos, the new words x_n .. x_{n+W-1} depend
-// only on words older than x_n, so one step produces S = min(W, lanes * K)
-// outputs at once: every lane loads its taps for K outputs, computes, writes
-// the new words to LDS and the tempered outputs to HBM, then the group
-// synchronises once.  The LDS buffer is linear (x_n at a fixed offset from
-// the step's head) so that every tap is an immediate offset from one or two
-// per-lane base registers; when the head reaches the end of the buffer the
-// last N words are copied back to the front.
+// only on words older than x_n, so one step produces up to W outputs at once:
+// every lane loads its taps for up to K outputs, computes, writes the new
+// words to LDS and the tempered outputs to HBM, then the group synchronises
+// once.  Steps are rounded down to multiples of 32 words when W >= 64 so that
+// the stores of a step cover whole 128-byte lines.  The LDS buffer is linear
+// (x_n at a fixed offset from the step's head) so that every tap is an
+// immediate offset from one or two per-lane base registers; when the head
+// reaches the end of the buffer the last N words are copied to the front.
+//
+// Jump-ahead.  A work item may start from any state: a long stream is cut
+// into segments whose start states jump_kernel computes from the stream's
+// first words (the generator is GF(2)-linear, so the state J outputs ahead
+// is a fixed XOR-combination of consecutive words, given by x^(J-1) mod p
+// for a polynomial p that annihilates the word sequence).  Each segment
+// checks that its final state equals the next segment's jumped start state.
 //
 // Work is bit-level GF(2) arithmetic: no MFMA.  The bound is HBM write
 // bandwidth (4 bytes per output), with VALU and LDS close behind.
@@ -55,40 +63,50 @@ struct Core {
     static_assert(BUF >= 2 * N + SMAX, "compaction would overlap");
     static constexpr int LDS_WORDS = BUF + 32;  // + recursion and output tables
 
-    // Advance one stream by `count` outputs written to out[0..count).
+    // Advance one stream by item.count outputs.
     template <bool F32>
     static __device__ __forceinline__ void run(const uint32_t *__restrict__ prm,
-                                               uint32_t *__restrict__ st,
-                                               uint32_t *__restrict__ out,
-                                               uint64_t count,
-                                               uint32_t *__restrict__ buf,
-                                               uint32_t lane) {
+                                               const BatchItem &item,
+                                               uint32_t *__restrict__ buf, uint32_t lane,
+                                               uint32_t *__restrict__ err) {
         uint32_t *__restrict__ tbl = buf + BUF;
         const uint32_t pos = prm[P_POS];
         const uint32_t sh1 = prm[P_SH1];
         const uint32_t sh2 = prm[P_SH2];
         const uint32_t mask = prm[P_MASK];
         const uint32_t W = N - pos;
+        const uint64_t count = item.count;
+        const uint32_t *st_in = reinterpret_cast<const uint32_t *>(item.state_in);
+        uint32_t *st_out = reinterpret_cast<uint32_t *>(item.state_out);
+        gptr<uint32_t> raw = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.raw));
+        const bool want_raw = (item.mode & MODE_RAW) != 0;
 
         group_sync<TPS>();  // previous user of this buffer is done with it
-        for (uint32_t i = lane; i < N; i += TPS) buf[i] = st[i];
+        for (uint32_t i = lane; i < N; i += TPS) {
+            const uint32_t v = st_in[i];
+            buf[i] = v;
+            if (want_raw) raw[i] = v;
+        }
         if (lane < 16) {
             tbl[lane] = prm[P_REC + lane];
             tbl[16 + lane] = prm[(F32 ? P_FLT : P_TMP) + lane];
         }
         group_sync<TPS>();
 
-        const uint32_t smax = W < (uint32_t)SMAX ? W : (uint32_t)SMAX;
+        // Full steps: W rounded down to whole 128-byte lines when wide.
+        uint32_t smax = W >= 64 ? (W & ~31u) : W;
+        if (smax > (uint32_t)SMAX) smax = SMAX;
         uint32_t h = N;  // buffer index of the next new word
         uint64_t done = 0;
-        gptr<uint32_t> gout = (gptr<uint32_t>)(out);
+        gptr<uint32_t> gout = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.out));
         while (done < count) {
             const uint64_t rem = count - done;
             const uint32_t S = rem < smax ? (uint32_t)rem : smax;
-            // Every lane computes all K words of a full-width step, so keep
-            // h + SMAX inside the buffer: the loads and LDS writes of lanes
-            // beyond S then stay in bounds (their words are rewritten by the
-            // next step before anything reads them).
+            const uint32_t keff = (S + TPS - 1) / TPS;
+            // Lanes compute every word of their k < keff, so keep h + SMAX
+            // inside the buffer: loads and LDS writes of lanes beyond S then
+            // stay in bounds (their words are rewritten by the next step
+            // before anything reads them).
             if (h + SMAX > (uint32_t)BUF) {
                 for (uint32_t i = lane; i < N; i += TPS) buf[i] = buf[h - N + i];
                 group_sync<TPS>();
@@ -100,59 +118,86 @@ struct Core {
             uint32_t a[K], b[K], hh[K], c[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                a[k] = q[k * TPS];
-                b[k] = q[k * TPS + 1];
-                hh[k] = qp[k * TPS];
-                c[k] = qp[k * TPS + 1];
+                if (k < (int)keff) {
+                    a[k] = q[k * TPS];
+                    b[k] = q[k * TPS + 1];
+                    hh[k] = qp[k * TPS];
+                    c[k] = qp[k * TPS + 1];
+                }
             }
             uint32_t x[K], r[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                uint32_t X = (a[k] & mask) ^ b[k];
-                X ^= X << sh1;
-                const uint32_t Y = X ^ (c[k] >> sh2);
-                x[k] = Y ^ tbl[Y & 15u];
-                uint32_t H = hh[k] ^ (hh[k] >> 16);
-                H ^= H >> 8;
-                const uint32_t tv = tbl[16 + (H & 15u)];
-                if constexpr (F32)
-                    r[k] = __float_as_uint(__uint_as_float((x[k] >> 9) ^ tv) - 1.0f);
-                else
-                    r[k] = x[k] ^ tv;
+                if (k < (int)keff) {
+                    uint32_t X = (a[k] & mask) ^ b[k];
+                    X ^= X << sh1;
+                    const uint32_t Y = X ^ (c[k] >> sh2);
+                    x[k] = Y ^ tbl[Y & 15u];
+                    uint32_t H = hh[k] ^ (hh[k] >> 16);
+                    H ^= H >> 8;
+                    const uint32_t tv = tbl[16 + (H & 15u)];
+                    if constexpr (F32)
+                        r[k] = __float_as_uint(__uint_as_float((x[k] >> 9) ^ tv) - 1.0f);
+                    else
+                        r[k] = x[k] ^ tv;
+                }
             }
             uint32_t *w = buf + (h + lane);
 #pragma unroll
-            for (int k = 0; k < K; ++k) w[k * TPS] = x[k];
+            for (int k = 0; k < K; ++k)
+                if (k < (int)keff) w[k * TPS] = x[k];
             gptr<uint32_t> o = gout + done + lane;
-            if (S == (uint32_t)SMAX) {
+            if (S == keff * TPS) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) __builtin_nontemporal_store(r[k], o + k * TPS);
+                for (int k = 0; k < K; ++k)
+                    if (k < (int)keff) __builtin_nontemporal_store(r[k], o + k * TPS);
             } else {
 #pragma unroll
                 for (int k = 0; k < K; ++k)
-                    if (lane + k * TPS < S) __builtin_nontemporal_store(r[k], o + k * TPS);
+                    if (k < (int)keff && lane + k * TPS < S)
+                        __builtin_nontemporal_store(r[k], o + k * TPS);
+            }
+            if (want_raw) {
+                gptr<uint32_t> rw = raw + N + done + lane;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (k < (int)keff && lane + k * TPS < S) rw[k * TPS] = x[k];
             }
             group_sync<TPS>();
             h += S;
             done += S;
         }
-        for (uint32_t i = lane; i < N; i += TPS) st[i] = buf[h - N + i];
+        if (st_out != nullptr)
+            for (uint32_t i = lane; i < N; i += TPS) st_out[i] = buf[h - N + i];
+        if (item.mode & MODE_VERIFY) {
+            // the end state must equal the next segment's jumped start state
+            const uint32_t *ref = reinterpret_cast<const uint32_t *>(item.verify);
+            uint32_t bad = 0;
+            for (uint32_t i = lane; i < N; i += TPS) bad |= (buf[h - N + i] != ref[i]) ? 1u : 0u;
+            if (bad) atomicAdd(err, 1u);
+        }
     }
 };
 
-// Persistent / plain generation kernel.  Each group (a wave when TPS == 64,
-// else the workgroup) takes work items until none are left.
-//  items != nullptr : batch mode, items claimed through *counter.
-//  items == nullptr : plain mode, item i is stream i with `plain_count`
-//                     outputs at plain_out + i * plain_count, groups take
-//                     items i = group, group + n_groups, ...
+// Generation kernel.  Each group (a wave when TPS == 64, else the workgroup)
+// takes work items until none are left.
+//  persistent != 0 : items are claimed in order through *counter.
+//  persistent == 0 : group g takes items g, g + n_groups, ...
+// Plain mode (items == nullptr): item i is stream i, advanced in place in
+// its state row by plain_count outputs written at plain_out + i*plain_count.
+struct PlainArgs {
+    uint32_t *states;
+    uint32_t stride;
+    uint32_t mode;
+    uint32_t *out;
+    uint64_t count;
+};
+
 template <int N, int TPS, int K, int WPB>
 __global__ void __launch_bounds__(TPS == 64 ? 64 * WPB : TPS)
-gen_kernel(const uint32_t *__restrict__ params, uint32_t *__restrict__ states,
-           uint32_t stride, const BatchItem *__restrict__ items,
-           uint32_t n_items, uint32_t *__restrict__ counter,
-           uint32_t *__restrict__ plain_out, uint64_t plain_count,
-           uint32_t plain_f32) {
+gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
+           uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
+           uint32_t persistent, PlainArgs plain) {
     using C = Core<N, TPS, K>;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_claim;
@@ -164,7 +209,7 @@ gen_kernel(const uint32_t *__restrict__ params, uint32_t *__restrict__ states,
     uint32_t it = blockIdx.x * (TPS == 64 ? WPB : 1) + wave;
 
     while (true) {
-        if (items != nullptr) {
+        if (persistent) {
             if constexpr (TPS == 64) {
                 uint32_t v = 0;
                 if (lane == 0) v = atomicAdd(counter, 1u);
@@ -177,38 +222,90 @@ gen_kernel(const uint32_t *__restrict__ params, uint32_t *__restrict__ states,
             }
         }
         if (it >= n_items) break;
-        uint32_t stream;
-        uint32_t f32;
-        uint64_t count;
-        uint32_t *out;
+        BatchItem item;
         if (items != nullptr) {
-            const BatchItem item = items[it];
-            stream = item.stream;
-            f32 = item.dtype;
-            count = item.count;
-            out = reinterpret_cast<uint32_t *>(item.out);
+            item = items[it];
         } else {
-            stream = it;
-            f32 = plain_f32;
-            count = plain_count;
-            out = plain_out + (uint64_t)it * plain_count;
+            uint32_t *row = plain.states + (uint64_t)it * plain.stride;
+            item.stream = it;
+            item.mode = plain.mode;
+            item.count = plain.count;
+            item.out = (uint64_t)(uintptr_t)(plain.out + (uint64_t)it * plain.count);
+            item.state_in = item.state_out = (uint64_t)(uintptr_t)row;
+            item.raw = item.verify = item.flag = item.countdown = 0;
         }
-        const uint32_t *prm = params + (uint64_t)stream * P_WORDS;
-        uint32_t *st = states + (uint64_t)stream * stride;
-        if (f32)
-            C::template run<true>(prm, st, out, count, buf, lane);
-        else
-            C::template run<false>(prm, st, out, count, buf, lane);
-        if (items == nullptr) {
-            it += n_groups;
-        } else if (items[it].flag != 0) {
-            // Publish completion of this item to the host: every lane's
-            // output and state stores are made visible system-wide first.
+        const uint32_t *prm = params + (uint64_t)item.stream * P_WORDS;
+        if (item.count > 0) {
+            if (item.mode & MODE_F32)
+                C::template run<true>(prm, item, buf, lane, err);
+            else
+                C::template run<false>(prm, item, buf, lane, err);
+        }
+        if (item.flag != 0) {
+            // Publish completion of the request to the host once its last
+            // segment is done: every lane's output and state stores are made
+            // visible system-wide first.
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
             group_sync<TPS>();
-            if (lane == 0)
-                __hip_atomic_store(reinterpret_cast<uint32_t *>(items[it].flag), 1u,
-                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            if (lane == 0) {
+                bool last = true;
+                if (item.countdown != 0)
+                    last = __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(item.countdown),
+                                                  0xFFFFFFFFu, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT) == 1u;
+                if (last)
+                    __hip_atomic_store(reinterpret_cast<uint32_t *>(item.flag), 1u,
+                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
+        }
+        if (!persistent) it += n_groups;
+    }
+}
+
+// Jump evaluation: out[m] = XOR over the set bits i < D of g of raw[1+i+m],
+// for m < M.  One 256-thread workgroup per item; the words are staged
+// through LDS in chunks of JUMP_CH coefficients plus the output tail, and
+// lane t owns output words m = t + 256 j of the current pass.
+constexpr int JUMP_THREADS = 256;
+constexpr int JUMP_CH = 4096;   // coefficients per LDS chunk
+constexpr int JUMP_MT = 1024;   // output words per pass (4 per lane)
+
+__global__ void __launch_bounds__(JUMP_THREADS)
+jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
+    __shared__ uint32_t base[JUMP_CH + JUMP_MT];
+    const uint32_t t = threadIdx.x;
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const JumpItem jit = items[it];
+        const uint32_t *raw = reinterpret_cast<const uint32_t *>(jit.raw) + 1;
+        const uint32_t *g = reinterpret_cast<const uint32_t *>(jit.poly);
+        uint32_t *out = reinterpret_cast<uint32_t *>(jit.out);
+        const uint32_t D = jit.nbits, M = jit.m;
+        for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
+            const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
+            uint32_t acc[JUMP_MT / JUMP_THREADS] = {};
+            for (uint32_t i0 = 0; i0 < D; i0 += JUMP_CH) {
+                const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
+                __syncthreads();
+                for (uint32_t j = t; j < ch + mt; j += JUMP_THREADS) base[j] = raw[i0 + m0 + j];
+                __syncthreads();
+                const uint32_t nw = (ch + 31) / 32;
+                for (uint32_t w = 0; w < nw; ++w) {
+                    uint32_t bits = g[(i0 >> 5) + w];
+                    if (w == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
+                    while (bits) {
+                        const uint32_t i = 32 * w + (uint32_t)__builtin_ctz(bits);
+                        bits &= bits - 1u;
+#pragma unroll
+                        for (int j = 0; j < JUMP_MT / JUMP_THREADS; ++j)
+                            acc[j] ^= base[i + t + j * JUMP_THREADS];
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < JUMP_MT / JUMP_THREADS; ++j) {
+                const uint32_t m = t + j * JUMP_THREADS;
+                if (m < mt) out[m0 + m] = acc[j];
+            }
         }
     }
 }
@@ -232,9 +329,9 @@ __global__ void seed_kernel(const uint32_t *__restrict__ params,
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
-// Store-only fill: the achievable write bandwidth next to the generator.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Store-only fill: the achievable write bandwidth next to the generator.
 __global__ void __launch_bounds__(256)
 fill_kernel(u32x4 *__restrict__ out, uint64_t n_vec, uint32_t *__restrict__ tail,
             uint32_t n_tail, uint32_t value) {
@@ -261,21 +358,20 @@ static hipError_t launch_gen(const LaunchArgs &a) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    int grid = a.grid;
-    if (grid <= 0) {  // persistent: fill every CU to its occupancy
+    const int per_block = TPS == 64 ? WPB : 1;
+    const int need = (int)((a.n_items + per_block - 1) / per_block);
+    int grid = need > 0 ? need : 1;
+    if (a.persistent) {  // fill every CU to its occupancy, no more groups than items
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
         if (e != hipSuccess) return e;
         if (per_cu < 1) per_cu = 1;
-        grid = per_cu * a.num_cus;
-        // no more groups than items
-        const int per_block = TPS == 64 ? WPB : 1;
-        const int need = (int)((a.n_items + per_block - 1) / per_block);
-        if (need < grid) grid = need > 0 ? need : 1;
+        if (per_cu * a.num_cus < grid) grid = per_cu * a.num_cus;
     }
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, (hipStream_t)a.stream,
-                       a.params, a.states, a.stride, a.items, a.n_items, a.counter,
-                       a.plain_out, a.plain_count, a.plain_f32);
+    PlainArgs plain{a.plain_states, a.plain_stride, a.plain_mode, a.plain_out, a.plain_count};
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, (hipStream_t)a.stream, a.params,
+                       a.items, a.n_items, a.counter, a.err, a.persistent ? 1u : 0u, plain);
     return hipGetLastError();
 }
 
@@ -332,16 +428,28 @@ hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs
     return hipSuccess;
 }
 
+hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s) {
+    if (n_items == 0) return hipSuccess;
+    int grid = (int)n_items;
+    const int cap = num_cus * 8;
+    if (grid > cap) grid = cap;
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(JUMP_THREADS), 0, s, items, n_items);
+    return hipGetLastError();
+}
+
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s) {
     const int threads = 256;
     const int grid = (int)((n_streams + threads - 1) / threads);
+    (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(seed_kernel, dim3(grid), dim3(threads), 0, s, params, states,
                        stride, n_streams);
     return hipGetLastError();
 }
 
 hipError_t launch_reset(uint32_t *counter, hipStream_t s) {
+    (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
     return hipGetLastError();
 }
@@ -353,6 +461,7 @@ hipError_t launch_fill(uint32_t *out, uint64_t n_words, uint32_t value, int num_
     uint64_t want = (n_vec + 255) / 256;
     uint64_t cap = (uint64_t)num_cus * 8;
     int grid = (int)(want < cap ? (want > 0 ? want : 1) : cap);
+    (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(fill_kernel, dim3(grid), dim3(256), 0, s,
                        reinterpret_cast<u32x4 *>(out), n_vec, out + n_vec * 4, n_tail, value);
     return hipGetLastError();

@@ -42,7 +42,7 @@ using Clock = std::chrono::steady_clock;
 
 enum ReqState { R_QUEUED, R_ADMITTED, R_LAUNCHED, R_DONE, R_FAILED, R_CANCELED };
 
-struct Request {
+struct Req {
     uint64_t ticket = 0;
     int32_t stream = 0;
     uint64_t count = 0;
@@ -120,6 +120,7 @@ struct Server {
     uint32_t *d_states = nullptr;
     int stride = 0, n_streams = 0;
     char *d_pool = nullptr;   // output region (after the slot workspaces)
+    size_t ws_bytes = 0;      // workspace per slot
     std::shared_ptr<ParamSet> ps;
     mtgp_server_opts opts{};
     int device = 0;
@@ -128,7 +129,7 @@ struct Server {
     std::mutex mu;
     std::condition_variable cv_work;   // wakes the loop
     std::condition_variable cv_done;   // wakes waiters
-    std::unordered_map<uint64_t, Request> reqs;
+    std::unordered_map<uint64_t, Req> reqs;
     std::deque<uint64_t> pending;      // tickets in submission order
     std::unordered_map<int32_t, std::deque<uint64_t>> per_stream;
     std::vector<uint8_t> stream_busy;
@@ -185,7 +186,7 @@ struct Server {
             const uint64_t t = now();
             uint64_t cur = off;
             for (uint64_t tk : group) {
-                Request &r = reqs[tk];
+                Req &r = reqs[tk];
                 r.state = R_ADMITTED;
                 r.t_admit = t;
                 r.off = cur;
@@ -204,46 +205,37 @@ struct Server {
     int launch_locked(int si) {
         Slot &sl = slots[si];
         const int n = (int)ready.size();
-        std::vector<mtgp_work> work(n);
+        std::vector<mtgp::Request> work((size_t)n);
         for (int i = 0; i < n; ++i) {
-            const Request &r0 = reqs[ready[i].front()];
+            const Req &r0 = reqs[ready[i].front()];
             uint64_t total = 0;
             for (uint64_t tk : ready[i]) total += reqs[tk].count;
-            work[i].stream_id = r0.stream;
-            work[i].dtype = (uint32_t)r0.dtype;
-            work[i].count = total;
-            work[i].d_out = d_pool + r0.off;
+            sl.flags[i] = 0u;
+            work[i] = mtgp::Request{r0.stream, (uint32_t)r0.dtype, total, d_pool + r0.off,
+                                    (uint64_t)(uintptr_t)&sl.flags[i]};
         }
-        const mtgp_tuning tun = tuning_for(ps->N);
-        std::vector<BatchItem> items;
-        std::vector<int> order;
-        plan_items_indexed(*ps, tun, work.data(), n, items, order);
-        for (size_t j = 0; j < items.size(); ++j) {
-            sl.flags[j] = 0u;
-            items[j].flag = (uint64_t)(uintptr_t)&sl.flags[j];
-        }
-        sl.item_tickets.assign(items.size(), {});
-        sl.item_done.assign(items.size(), 0);
+        sl.item_tickets.assign((size_t)n, {});
+        sl.item_done.assign((size_t)n, 0);
         const uint64_t t = now();
-        for (size_t j = 0; j < items.size(); ++j) {
-            sl.item_tickets[j] = ready[order[j]];
-            for (uint64_t tk : sl.item_tickets[j]) {
-                Request &r = reqs[tk];
+        for (int i = 0; i < n; ++i) {
+            sl.item_tickets[i] = ready[i];
+            for (uint64_t tk : sl.item_tickets[i]) {
+                Req &r = reqs[tk];
                 r.state = R_LAUNCHED;
                 r.t_launch = t;
                 r.slot = si;
-                r.item = (int)j;
+                r.item = i;
             }
         }
         ready.clear();
-        sl.n_items = (int)items.size();
+        sl.n_items = n;
         sl.n_done = 0;
         sl.busy = true;
         int rc;
         {
             std::lock_guard<std::mutex> lk(sl.stage->mu);
-            rc = launch_planned(*ps, d_params, d_states, stride, items, sl.d_ws, sl.hs, tun,
-                                false, *sl.stage);
+            rc = run_batch(ps, d_params, d_states, stride, work, sl.d_ws, ws_bytes, sl.hs,
+                           tuning_for(ps->N), false, *sl.stage);
         }
         if (rc == MTGP_OK) {
             hipError_t e = hipEventRecord(sl.done, sl.hs);
@@ -257,7 +249,7 @@ struct Server {
         return rc;
     }
 
-    void finish_locked(Request &r, ReqState st) {
+    void finish_locked(Req &r, ReqState st) {
         r.state = st;
         r.t_done = now();
         stream_busy[r.stream] = 0;
@@ -353,7 +345,7 @@ struct Server {
             if (sl.busy) (void)hipStreamSynchronize(sl.hs);
         reap_locked();
         for (auto &kv : reqs) {
-            Request &r = kv.second;
+            Req &r = kv.second;
             if (r.state == R_QUEUED || r.state == R_ADMITTED) finish_locked(r, R_CANCELED);
             if (r.state == R_LAUNCHED) finish_locked(r, R_FAILED);
         }
@@ -383,12 +375,14 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states, int state_strid
                     state_stride, ps->N);
     if (!d_pool || ((uintptr_t)d_pool & 255u))
         return fail(MTGP_EINVAL, "d_pool must be non-NULL and 256-byte aligned");
-    mtgp_server_opts o{4, 256, 1 << 20, 20000};
+    mtgp_server_opts o{4, 256, 1 << 20, 20000, 64ull << 20};
     if (opts) o = *opts;
     if (o.max_inflight_batches < 1 || o.max_inflight_batches > 16 || o.max_batch_items < 1 ||
         o.max_queue < 1)
         return fail(MTGP_EINVAL, "bad server options");
-    const size_t ws = (batch_ws_bytes(o.max_batch_items) + 255) / 256 * 256;
+    size_t ws = std::max<size_t>(batch_min_ws_bytes(o.max_batch_items),
+                                 (size_t)o.workspace_bytes_per_batch);
+    ws = (ws + 255) / 256 * 256;
     const uint64_t reserved = (uint64_t)ws * (uint64_t)o.max_inflight_batches;
     if (pool_bytes <= reserved + 256)
         return fail(MTGP_EINVAL, "pool of %llu bytes is too small (workspaces need %llu)",
@@ -419,6 +413,7 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states, int state_strid
         if (e != hipSuccess) rc = hip_fail(e, "server slot setup");
     }
     S.d_pool = (char *)d_pool + reserved;
+    S.ws_bytes = ws;
     S.pool = std::make_unique<Pool>(pool_bytes - reserved);
     if (rc != MTGP_OK) {
         for (Slot &sl : S.slots) {
@@ -448,7 +443,7 @@ int mtgp_submit(mtgp_server *srv, int32_t stream_id, uint64_t count, int dtype,
                     (unsigned long long)(count * 4), (unsigned long long)S.pool->size());
     if (S.stop) return fail(MTGP_ECANCELED, "server is shutting down");
     if ((int)S.queued >= S.opts.max_queue) return fail(MTGP_EAGAIN, "queue full");
-    Request r;
+    Req r;
     r.ticket = S.next_ticket++;
     r.stream = stream_id;
     r.count = count;
@@ -470,7 +465,7 @@ int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state, const void **d_resu
     std::lock_guard<std::mutex> lk(S.mu);
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) return fail(MTGP_ENOENT, "ticket %llu unknown", (unsigned long long)ticket);
-    const Request &r = it->second;
+    const Req &r = it->second;
     if (d_result) *d_result = nullptr;
     switch (r.state) {
         case R_DONE:
@@ -516,7 +511,7 @@ int mtgp_release(mtgp_server *srv, uint64_t ticket) {
     std::lock_guard<std::mutex> lk(S.mu);
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) return fail(MTGP_ENOENT, "ticket %llu unknown", (unsigned long long)ticket);
-    Request &r = it->second;
+    Req &r = it->second;
     if (r.state == R_ADMITTED || r.state == R_LAUNCHED)
         return fail(MTGP_EAGAIN, "ticket %llu is still being generated", (unsigned long long)ticket);
     if (r.state == R_QUEUED) {
@@ -540,7 +535,7 @@ int mtgp_request_times(mtgp_server *srv, uint64_t ticket, uint64_t *t_submit, ui
     std::lock_guard<std::mutex> lk(S.mu);
     auto it = S.reqs.find(ticket);
     if (it == S.reqs.end()) return fail(MTGP_ENOENT, "ticket %llu unknown", (unsigned long long)ticket);
-    const Request &r = it->second;
+    const Req &r = it->second;
     if (t_submit) *t_submit = r.t_submit;
     if (t_admit) *t_admit = r.t_admit;
     if (t_launch) *t_launch = r.t_launch;
@@ -562,12 +557,8 @@ int mtgp_server_destroy(mtgp_server *srv) {
         if (sl.flags) (void)hipHostFree(sl.flags);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.hs) (void)hipStreamDestroy(sl.hs);
-        if (sl.stage) {
-            if (sl.stage->host) (void)hipHostFree(sl.stage->host);
-            if (sl.stage->done) (void)hipEventDestroy(sl.stage->done);
-        }
     }
-    delete srv;
+    delete srv;  // slot staging buffers are released by their destructors
     return rc;
 }
 

@@ -41,18 +41,20 @@ class Work(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("threads_per_stream", ctypes.c_int), ("outputs_per_lane", ctypes.c_int),
-                ("workgroup_size", ctypes.c_int)]
+                ("workgroup_size", ctypes.c_int), ("jump_target_steps", ctypes.c_int)]
 
     def as_tuple(self):
-        return (self.threads_per_stream, self.outputs_per_lane, self.workgroup_size)
+        return (self.threads_per_stream, self.outputs_per_lane, self.workgroup_size,
+                self.jump_target_steps)
 
     def __repr__(self):
-        return "Tuning(tps=%d, k=%d, wg=%d)" % self.as_tuple()
+        return "Tuning(tps=%d, k=%d, wg=%d, jump=%d)" % self.as_tuple()
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("max_inflight_batches", ctypes.c_int), ("max_batch_items", ctypes.c_int),
-                ("max_queue", ctypes.c_int), ("batch_window_ns", ctypes.c_uint64)]
+                ("max_queue", ctypes.c_int), ("batch_window_ns", ctypes.c_uint64),
+                ("workspace_bytes_per_batch", ctypes.c_uint64)]
 
 
 _lib = None
@@ -72,14 +74,17 @@ _SIGS = {
     "mtgp_generate_f32": ([_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _VP, _VP],
                           ctypes.c_int),
     "mtgp_batch_workspace_bytes": ([ctypes.c_int], ctypes.c_size_t),
-    "mtgp_generate_batch": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP, _VP],
-                            ctypes.c_int),
+    "mtgp_batch_workspace_query": ([_VP, ctypes.POINTER(Work), ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "mtgp_generate_batch": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP,
+                             ctypes.c_size_t, _VP], ctypes.c_int),
+    "mtgp_batch_errors": ([_VP, _VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
     "mtgp_get_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
     "mtgp_set_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
     "mtgp_tuning_candidates": ([ctypes.c_uint32, ctypes.POINTER(Tuning), ctypes.c_int],
                                ctypes.c_int),
     "mtgp_autotune": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP,
-                       ctypes.c_int, _VP, ctypes.POINTER(Tuning),
+                       ctypes.c_size_t, ctypes.c_int, _VP, ctypes.POINTER(Tuning),
                        ctypes.POINTER(ctypes.c_float), ctypes.c_int], ctypes.c_int),
     "mtgp_state_export": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
     "mtgp_state_import": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
@@ -213,10 +218,34 @@ def make_work(items) -> ctypes.Array:
     return arr, len(items)
 
 
-def generate_batch(d_params, d_states, stride: int, items, d_workspace, stream=None) -> None:
+def _nbytes(t) -> int:
+    if hasattr(t, "numel"):
+        return int(t.numel() * t.element_size())
+    raise TypeError("pass workspace_bytes for a raw workspace address")
+
+
+def batch_workspace_query(d_params, items) -> int:
     arr, n = items if isinstance(items, tuple) else make_work(items)
+    out = ctypes.c_size_t()
+    _check(lib().mtgp_batch_workspace_query(_ptr(d_params), arr, n, ctypes.byref(out)),
+           "mtgp_batch_workspace_query")
+    return int(out.value)
+
+
+def generate_batch(d_params, d_states, stride: int, items, d_workspace, stream=None,
+                   workspace_bytes=None) -> None:
+    arr, n = items if isinstance(items, tuple) else make_work(items)
+    wsb = _nbytes(d_workspace) if workspace_bytes is None else int(workspace_bytes)
     _check(lib().mtgp_generate_batch(_ptr(d_params), _ptr(d_states), stride, arr, n,
-                                     _ptr(d_workspace), _stream(stream)), "mtgp_generate_batch")
+                                     _ptr(d_workspace), wsb, _stream(stream)),
+           "mtgp_generate_batch")
+
+
+def batch_errors(d_workspace, stream=None) -> int:
+    n = ctypes.c_uint32()
+    _check(lib().mtgp_batch_errors(_ptr(d_workspace), _stream(stream), ctypes.byref(n)),
+           "mtgp_batch_errors")
+    return int(n.value)
 
 
 def get_tuning(mexp: int) -> Tuning:
@@ -225,8 +254,10 @@ def get_tuning(mexp: int) -> Tuning:
     return t
 
 
-def set_tuning(mexp: int, tps: int, k: int, wg: int) -> None:
-    t = Tuning(tps, k, wg)
+def set_tuning(mexp: int, tps: int, k: int, wg: int, jump_target_steps=None) -> None:
+    if jump_target_steps is None:
+        jump_target_steps = get_tuning(mexp).jump_target_steps
+    t = Tuning(tps, k, wg, jump_target_steps)
     _check(lib().mtgp_set_tuning(mexp, ctypes.byref(t)), "mtgp_set_tuning")
 
 
@@ -237,17 +268,18 @@ def tuning_candidates(mexp: int):
     return [arr[i] for i in range(n)]
 
 
-def autotune(d_params, d_states, stride: int, items, d_scratch, reps: int = 2, stream=None):
-    """Times every compiled candidate on this batch; returns (best, {tuple: ms})."""
+def autotune(d_params, d_states, stride: int, items, d_scratch, reps: int = 2, stream=None,
+             scratch_bytes=None):
+    """Times every compiled candidate (then jump targets) on this batch;
+    returns (best, per-candidate ms)."""
     arr, n = items if isinstance(items, tuple) else make_work(items)
     best = Tuning()
-    cands = None
     ms = (ctypes.c_float * 64)()
+    sb = _nbytes(d_scratch) if scratch_bytes is None else int(scratch_bytes)
     _check(lib().mtgp_autotune(_ptr(d_params), _ptr(d_states), stride, arr, n, _ptr(d_scratch),
-                               reps, _stream(stream), ctypes.byref(best), ms, 64),
+                               sb, reps, _stream(stream), ctypes.byref(best), ms, 64),
            "mtgp_autotune")
-    # candidate order is mtgp_tuning_candidates order for this mexp
-    return best, ms
+    return best, list(ms)
 
 
 def state_export(d_params, d_states, stride: int, n_streams: int, n_words: int,
@@ -307,13 +339,19 @@ class Generators:
     def load_states(self, host_states: np.ndarray) -> None:
         state_import(self.d_params, self.d_states, self.stride, host_states)
 
-    def workspace(self, n_items: int):
+    def workspace(self, items):
+        """Device workspace sized for `items` (a list, or a count for the
+        minimum without jump-ahead splitting)."""
         import torch
-        return torch.empty(batch_workspace_bytes(n_items), dtype=torch.uint8, device=self.device)
+        if isinstance(items, int):
+            nbytes = batch_workspace_bytes(items)
+        else:
+            nbytes = batch_workspace_query(self.d_params, list(items))
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
 
     def batch(self, items, workspace=None, stream=None):
         items = list(items)
-        ws = self.workspace(len(items)) if workspace is None else workspace
+        ws = self.workspace(items) if workspace is None else workspace
         generate_batch(self.d_params, self.d_states, self.stride, items, ws, stream)
         return ws
 
@@ -322,3 +360,64 @@ class Generators:
             release_params(self.d_params)
         except MTGPError:
             pass
+
+
+class Server:
+    """Serving loop over the resident states of `gens` (a Generators).
+
+    pool_bytes of device memory are allocated with torch for outputs and
+    launch workspaces; requests are admitted while their outputs fit."""
+
+    def __init__(self, gens: Generators, pool_bytes: int, inflight: int = 4,
+                 max_batch_items: int = 256, max_queue: int = 1 << 20,
+                 batch_window_ns: int = 20000, workspace_bytes_per_batch: int = 64 << 20):
+        import torch
+        self.gens = gens
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=gens.device)
+        opts = ServerOpts(inflight, max_batch_items, max_queue, batch_window_ns,
+                          workspace_bytes_per_batch)
+        h = ctypes.c_void_p()
+        _check(lib().mtgp_server_create(_ptr(gens.d_params), _ptr(gens.d_states), gens.stride,
+                                        gens.n, _ptr(self.pool), int(pool_bytes),
+                                        ctypes.byref(opts), ctypes.byref(h)),
+               "mtgp_server_create")
+        self.h = h
+
+    def submit(self, stream_id: int, count: int, dtype: int = U32) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().mtgp_submit(self.h, int(stream_id), int(count), int(dtype),
+                                 ctypes.byref(t)), "mtgp_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        st = ctypes.c_int()
+        ptr = ctypes.c_void_p()
+        _check(lib().mtgp_poll(self.h, ticket, ctypes.byref(st), ctypes.byref(ptr)), "mtgp_poll")
+        return int(st.value), (int(ptr.value) if ptr.value else 0)
+
+    def wait(self, ticket: int, timeout_ns: int = 0) -> None:
+        _check(lib().mtgp_wait(self.h, ticket, int(timeout_ns)), "mtgp_wait")
+
+    def release(self, ticket: int) -> None:
+        _check(lib().mtgp_release(self.h, ticket), "mtgp_release")
+
+    def times(self, ticket: int):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().mtgp_request_times(self.h, ticket, *[ctypes.byref(x) for x in v]),
+               "mtgp_request_times")
+        return tuple(int(x.value) for x in v)
+
+    def result(self, ticket: int, count: int, dtype: int = U32):
+        """Copy of a finished request's outputs as a torch tensor."""
+        import torch
+        state, ptr = self.poll(ticket)
+        if state != DONE:
+            raise RuntimeError("ticket %d not done" % ticket)
+        off = ptr - self.pool.data_ptr()
+        raw = self.pool[off:off + 4 * count].clone()
+        return raw.view(torch.float32 if dtype == F32 else torch.int32)
+
+    def close(self) -> None:
+        if self.h:
+            _check(lib().mtgp_server_destroy(self.h), "mtgp_server_destroy")
+            self.h = None

@@ -1,0 +1,134 @@
+"""GPU parity of jump-ahead splitting: a request cut into segments whose start
+states are jumped must give exactly the outputs and final state of the
+unsplit stream (and of the CPU oracle), and every segment's end-state check
+must pass."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_07701_amd import mtgp, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    mtgp.lib()
+    return t
+
+
+def _host(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+class _Tune:
+    """Temporarily set the jump target for an exponent."""
+
+    def __init__(self, mexp, target):
+        self.mexp, self.target = mexp, target
+
+    def __enter__(self):
+        self.t0 = mtgp.get_tuning(self.mexp)
+        t = self.t0.as_tuple()
+        mtgp.set_tuning(self.mexp, t[0], t[1], t[2], self.target)
+
+    def __exit__(self, *exc):
+        mtgp.set_tuning(self.mexp, *self.t0.as_tuple())
+
+
+def _params(mexp, master):
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 6, master)
+    p[0, 1] = N - 2          # W = 2
+    p[1, 1] = 1              # W = N - 1
+    p[2, 1] = N - 33         # W = 33
+    return p
+
+
+@pytest.mark.parametrize("mexp,count", [(3217, 60000), (11213, 150000), (44497, 300000)])
+def test_split_batch_matches_oracle(torch, mexp, count):
+    _say("case split mexp=%d count=%d" % (mexp, count))
+    p = _params(mexp, 0x5EED + mexp)
+    seeds = np.arange(1, 7, dtype=np.uint32)
+    N = mexp // 32 + 1
+    counts = [count, count // 2 + 7, count, 3 * count // 4 + 1, 1000, count]
+    dts = [0, 1, 0, 1, 0, 1]
+    with _Tune(mexp, 64):
+        g = mtgp.Generators(p, seeds)
+        outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in counts]
+        items = [(k, dts[k], counts[k], outs[k]) for k in range(6)]
+        ws_full = mtgp.batch_workspace_query(g.d_params, items)
+        assert ws_full > mtgp.batch_workspace_bytes(6)      # it does split
+        ws = g.workspace(items)
+        for rep in range(2):                                 # continuation across calls
+            g.batch(items, ws)
+            got = [_host(o).copy() for o in outs]
+            assert mtgp.batch_errors(ws) == 0
+            if rep == 0:
+                states = np.stack([oracle.seed(int(s), N) for s in seeds])
+            for k in range(6):
+                o, states[k] = oracle.generate(p[k], states[k], counts[k], bool(dts[k]))
+                assert np.array_equal(got[k], np.asarray(o).view(np.uint32)), (rep, k)
+        assert np.array_equal(g.states_host(), states)
+        g.close()
+
+
+def test_split_equals_unsplit_and_small_workspace(torch):
+    """Same batch three ways: no splitting, full splitting, and splitting
+    limited by a workspace that is too small for the full plan."""
+    _say("case split vs unsplit")
+    mexp, count = 11213, 200000
+    p = workloads.make_params(mexp, 16, 0xAB)
+    seeds = np.arange(1, 17, dtype=np.uint32)
+    results = []
+    for target, ws_kind in ((0, "min"), (128, "full"), (128, "half")):
+        with _Tune(mexp, target):
+            g = mtgp.Generators(p, seeds)
+            out = torch.empty(16 * count, dtype=torch.int32, device="cuda")
+            items = [(k, k & 1, count, out.data_ptr() + 4 * k * count) for k in range(16)]
+            full = mtgp.batch_workspace_query(g.d_params, items)
+            nbytes = {"min": mtgp.batch_workspace_bytes(16), "full": full,
+                      "half": max(mtgp.batch_workspace_bytes(16), full // 3)}[ws_kind]
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            mtgp.generate_batch(g.d_params, g.d_states, g.stride, items, ws)
+            assert mtgp.batch_errors(ws) == 0
+            results.append((_host(out).copy(), g.states_host()))
+            g.close()
+    for r in results[1:]:
+        assert np.array_equal(r[0], results[0][0])
+        assert np.array_equal(r[1], results[0][1])
+
+
+def test_split_after_reseed_and_graph_replays(torch):
+    """Bench shape: re-seed, split batch replayed from the cached graph."""
+    _say("case reseed + replays")
+    mexp, count = 3217, 40000
+    p = workloads.make_params(mexp, 32, 0xCD)
+    seeds = np.arange(1, 33, dtype=np.uint32)
+    exp, _ = oracle.generate_many(p, np.stack([oracle.seed(int(s), 101) for s in seeds]),
+                                  count, False, threads=8)
+    with _Tune(mexp, 32):
+        g = mtgp.Generators(p, seeds)
+        out = torch.empty(32 * count, dtype=torch.int32, device="cuda")
+        items = [(k, 0, count, out.data_ptr() + 4 * k * count) for k in range(32)]
+        ws = g.workspace(items)
+        for rep in range(3):
+            g.reseed()
+            mtgp.generate_batch(g.d_params, g.d_states, g.stride, items, ws)
+            h = _host(out).reshape(32, count)
+            for k in range(32):
+                assert np.array_equal(h[k], exp[k]), (rep, k)
+        assert mtgp.batch_errors(ws) == 0
+        g.close()
