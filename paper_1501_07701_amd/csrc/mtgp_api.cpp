@@ -138,6 +138,17 @@ static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, voi
         b[P_MASK] = h[k].mask;
         b[P_W] = (uint32_t)N - h[k].pos;
         b[P_SEED] = seeds ? seeds[k] : 0u;
+        // a linear recursion table is a span of four basis words; the
+        // latency-bound small-step path then forms rec[Y & 15] in registers
+        bool lin = h[k].rec_tbl[0] == 0u;
+        for (int i = 1; i < 16 && lin; ++i) {
+            uint32_t v = 0;
+            for (int bit = 0; bit < 4; ++bit)
+                if ((i >> bit) & 1) v ^= h[k].rec_tbl[1 << bit];
+            lin = v == h[k].rec_tbl[i];
+        }
+        b[P_LIN] = lin ? 1u : 0u;
+        for (int bit = 0; bit < 4; ++bit) b[P_RB + bit] = h[k].rec_tbl[1 << bit];
         std::memcpy(b + P_REC, h[k].rec_tbl, 64);
         std::memcpy(b + P_TMP, h[k].tmp_tbl, 64);
         std::memcpy(b + P_FLT, h[k].flt_tbl, 64);

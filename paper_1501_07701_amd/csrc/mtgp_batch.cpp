@@ -9,10 +9,11 @@
 // state J+1 outputs ahead, x_{J+1} .. x_{J+N}, needs only x_1 .. x_{D+N}.
 // A split request therefore runs as
 //   A: a prefix item: the first P = D+1 outputs, also dumping x_0..x_{N+D};
-//   B: one jump item per later segment c: start state of output c*lseg,
-//      from g_c = x^(c*lseg - 1) mod p;
-//   C: every segment (the first one continues after the prefix), each
-//      checking its end state against the next segment's start state.
+//   B: one jump item per later segment, which starts at output c*lseg
+//      (c >= c0 = ceil((P+1)/lseg)): its state from g_c = x^(c*lseg-1) mod p;
+//   C: every segment (the first one continues after the prefix up to
+//      c0*lseg), each checking its end state against the next segment's
+//      start state.
 // p is found once per stream from its seed status: Berlekamp-Massey on two
 // linear functionals of 2*mexp+127 words (lcm of the two), then checked on
 // the device over mexp further positions; if the check fails all 32 bit
@@ -285,10 +286,14 @@ static void ensure_g(StreamJump &sj, uint64_t lseg, int cmax) {
 // ---------------------------------------------------------------- plan ----
 
 namespace {
+// A request split into C segments: segment 0 covers outputs [0, c0*lseg)
+// (the prefix [0, P) with P = D+1, then the rest), segment k >= 1 covers
+// [(c0+k-1)*lseg, (c0+k)*lseg) clipped to the request.
 struct Seg {
     int req;
     int C = 1;           // segments (1 = not split)
     uint64_t lseg = 0;
+    uint64_t c0 = 0;
     StreamJump *sj = nullptr;
 };
 
@@ -304,6 +309,32 @@ size_t batch_min_ws_bytes(int n_items) {
     // header + A/B (none) + C items + countdowns
     return 256 + al256((size_t)std::max(n_items, 0) * sizeof(BatchItem)) +
            al256((size_t)std::max(n_items, 0) * 4);
+}
+
+// Splits a request when it needs more than T dependent steps and the
+// stream's jump data is usable.
+static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_t T,
+                   const mtgp_tuning &t, Seg &g) {
+    g.C = 1;
+    g.sj = nullptr;
+    if (!T || !sj || sj->status != 1) return;
+    const uint64_t so = step_outputs(ps.W[r.stream], t);
+    if ((r.count + so - 1) / so <= T) return;
+    const uint64_t P = (uint64_t)sj->D + 1;
+    const uint64_t lseg = std::max<uint64_t>(64, pow2ceil(T * so));
+    const uint64_t c0 = (P + 1 + lseg - 1) / lseg;   // segment 0 keeps >= 1 output past P
+    const uint64_t cend = (r.count + lseg - 1) / lseg;
+    if (cend <= c0) return;
+    g.C = (int)(1 + cend - c0);
+    g.lseg = lseg;
+    g.c0 = c0;
+    g.sj = sj;
+}
+
+static bool wants_split(const ParamSet &ps, const Request &r, uint64_t T, const mtgp_tuning &t) {
+    if (!T) return false;
+    const uint64_t so = step_outputs(ps.W[r.stream], t);
+    return (r.count + so - 1) / so > T && r.count > (uint64_t)ps.mexp + 128;
 }
 
 static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_t n_req) {
@@ -466,14 +497,11 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
     if (!cached) {
         // which requests want splitting at the tuning's target
         const int N = ps->N;
-        const uint64_t minseg = pow2ceil((uint64_t)ps->mexp + 128);
         std::vector<int> want;
         uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
         for (size_t i = 0; i < reqs.size(); ++i) {
             segs[i].req = (int)i;
-            const uint64_t so = step_outputs(ps->W[reqs[i].stream], t);
-            if (T && reqs[i].count > 2 * minseg && (reqs[i].count + so - 1) / so > T)
-                want.push_back(reqs[i].stream);
+            if (wants_split(*ps, reqs[i], T, t)) want.push_back(reqs[i].stream);
         }
         if (!want.empty()) {
             int rc = ensure_jumps(ps, d_params, want, t, s);
@@ -489,23 +517,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         }
         // plan, doubling the target until the workspace fits
         while (true) {
-            for (size_t i = 0; i < reqs.size(); ++i) {
-                Seg &g = segs[i];
-                g.C = 1;
-                g.sj = nullptr;
-                if (!T) continue;
-                const Request &r = reqs[i];
-                const uint64_t so = step_outputs(ps->W[r.stream], t);
-                if (r.count <= 2 * minseg || (r.count + so - 1) / so <= T) continue;
-                StreamJump *sj = sjs[i];
-                if (!sj || sj->status != 1) continue;
-                const uint64_t lseg = std::max(minseg, pow2ceil(T * so));
-                const uint64_t C = (r.count + lseg - 1) / lseg;
-                if (C < 2) continue;
-                g.C = (int)C;
-                g.lseg = lseg;
-                g.sj = sj;
-            }
+            for (size_t i = 0; i < reqs.size(); ++i) decide(*ps, reqs[i], sjs[i], T, t, segs[i]);
             L = layout_for(*ps, segs, reqs.size());
             if (L.total <= ws_bytes || !T) break;
             T *= 2;
@@ -518,7 +530,10 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         std::vector<Seg *> split;
         for (Seg &g : segs)
             if (g.C > 1) split.push_back(&g);
-        parallel_for((int)split.size(), [&](int i) { ensure_g(*split[i]->sj, split[i]->lseg, split[i]->C); });
+        parallel_for((int)split.size(), [&](int i) {
+            const Seg &g = *split[i];
+            ensure_g(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1));
+        });
 
         // build the uploaded image [0, up_end): a zeroed header (claim
         // counters, error count), the item tables, countdowns, polynomials
@@ -566,13 +581,15 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
             a.raw = (uint64_t)(uintptr_t)raw;
             a.flag = a.countdown = 0;
             A.emplace_back((P + so - 1) / so, a);
-            // B: jumps
+            // B: jumps, segment k >= 1 starts at output (c0+k-1)*lseg and
+            // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words
             const size_t pw = ((size_t)D + 31) / 32;
-            for (int c = 1; c < g.C; ++c) {
+            for (int k = 1; k < g.C; ++k) {
+                const uint64_t c = g.c0 + (uint64_t)k - 1;
                 JumpItem j;
                 j.raw = (uint64_t)(uintptr_t)raw;
                 j.poly = (uint64_t)(uintptr_t)(ws + poly_off);
-                j.out = (uint64_t)(uintptr_t)(js + (size_t)c * N);
+                j.out = (uint64_t)(uintptr_t)(js + (size_t)k * N);
                 j.nbits = (uint32_t)D;
                 j.m = (uint32_t)N;
                 std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
@@ -580,15 +597,16 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
                 B.push_back(j);
             }
             // C: segments
-            for (int c = 0; c < g.C; ++c) {
-                const uint64_t beg = (uint64_t)c * g.lseg;
-                const uint64_t end = std::min<uint64_t>(r.count, beg + g.lseg);
-                const uint64_t start = c == 0 ? P : beg;
+            for (int k = 0; k < g.C; ++k) {
+                const uint64_t c = k == 0 ? 0 : g.c0 + (uint64_t)k - 1;
+                const uint64_t start = k == 0 ? P : c * g.lseg;
+                const uint64_t end = std::min<uint64_t>(r.count, k == 0 ? g.c0 * g.lseg
+                                                                        : (c + 1) * g.lseg);
                 BatchItem b = base_item(end - start, start);
-                b.state_in = (uint64_t)(uintptr_t)(js + (size_t)c * N);
-                if (c + 1 < g.C) {
+                b.state_in = (uint64_t)(uintptr_t)(js + (size_t)k * N);
+                if (k + 1 < g.C) {
                     b.mode |= MODE_VERIFY;
-                    b.verify = (uint64_t)(uintptr_t)(js + (size_t)(c + 1) * N);
+                    b.verify = (uint64_t)(uintptr_t)(js + (size_t)(k + 1) * N);
                 } else {
                     b.state_out = (uint64_t)(uintptr_t)row;
                 }
@@ -732,35 +750,23 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items, i
     if (rc) return rc;
     const mtgp_tuning t = tuning_for(ps->N);
     const uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
-    const uint64_t minseg = pow2ceil((uint64_t)ps->mexp + 128);
     std::vector<int> want;
     std::vector<Request> reqs = to_requests(h_items, n_items);
-    for (const Request &r : reqs) {
-        const uint64_t so = step_outputs(ps->W[r.stream], t);
-        if (T && r.count > 2 * minseg && (r.count + so - 1) / so > T) want.push_back(r.stream);
-    }
+    for (const Request &r : reqs)
+        if (wants_split(*ps, r, T, t)) want.push_back(r.stream);
     if (!want.empty()) {
         rc = ensure_jumps(ps, d_params, want, t, nullptr);
         if (rc) return rc;
     }
     std::vector<Seg> segs(reqs.size());
     for (size_t i = 0; i < reqs.size(); ++i) {
-        const Request &r = reqs[i];
-        segs[i].req = (int)i;
-        const uint64_t so = step_outputs(ps->W[r.stream], t);
-        if (!T || r.count <= 2 * minseg || (r.count + so - 1) / so <= T) continue;
         StreamJump *sj = nullptr;
         {
             std::lock_guard<std::mutex> lk(ps->jump_mu);
-            if (ps->jumps.size() == (size_t)ps->n) sj = ps->jumps[r.stream].get();
+            if (ps->jumps.size() == (size_t)ps->n) sj = ps->jumps[reqs[i].stream].get();
         }
-        if (!sj || sj->status != 1) continue;
-        const uint64_t lseg = std::max(minseg, pow2ceil(T * so));
-        const uint64_t C = (r.count + lseg - 1) / lseg;
-        if (C < 2) continue;
-        segs[i].C = (int)C;
-        segs[i].lseg = lseg;
-        segs[i].sj = sj;
+        segs[i].req = (int)i;
+        decide(*ps, reqs[i], sj, T, t, segs[i]);
     }
     *bytes = std::max(layout_for(*ps, segs, reqs.size()).total, batch_min_ws_bytes(n_items));
     return MTGP_OK;

@@ -17,6 +17,8 @@ enum : uint32_t {
     P_MASK = 5,
     P_W = 6,
     P_SEED = 7,
+    P_LIN = 8,     // 1 if the recursion table is GF(2)-linear (rec[i^j] = rec[i]^rec[j])
+    P_RB = 9,      // its basis: rec[1], rec[2], rec[4], rec[8] (words 9..12)
     P_REC = 16,
     P_TMP = 32,
     P_FLT = 48,

@@ -61,7 +61,167 @@ struct Core {
     static constexpr int SMAX = TPS * K;
     static constexpr int BUF = buf_words(N, SMAX);
     static_assert(BUF >= 2 * N + SMAX, "compaction would overlap");
+    static_assert(N > 64, "the small-step path assumes N > 64");
     static constexpr int LDS_WORDS = BUF + 32;  // + recursion and output tables
+
+    struct Step {  // per-item values, uniform across the group
+        uint32_t pos, sh1, sh2, mask, W;
+        uint32_t rb0, rb1, rb2, rb3;  // basis of a linear recursion table
+    };
+
+    // x = Y ^ rec[Y & 15]: from LDS, or for a linear table as the XOR of
+    // the basis words selected by the low four bits of Y (no LDS round trip
+    // on the dependent chain).
+    template <bool LIN>
+    static __device__ __forceinline__ uint32_t rec(const Step &p, const uint32_t *tbl,
+                                                   uint32_t Y) {
+        if constexpr (LIN) {
+            uint32_t r = (0u - (Y & 1u)) & p.rb0;
+            r ^= (0u - ((Y >> 1) & 1u)) & p.rb1;
+            r ^= (0u - ((Y >> 2) & 1u)) & p.rb2;
+            r ^= (0u - ((Y >> 3) & 1u)) & p.rb3;
+            return Y ^ r;
+        } else {
+            return Y ^ tbl[Y & 15u];
+        }
+    }
+
+    template <bool F32>
+    static __device__ __forceinline__ uint32_t temper(const uint32_t *tbl, uint32_t x,
+                                                      uint32_t hh) {
+        uint32_t H = hh ^ (hh >> 16);
+        H ^= H >> 8;
+        const uint32_t tv = tbl[16 + (H & 15u)];
+        if constexpr (F32)
+            return __float_as_uint(__uint_as_float((x >> 9) ^ tv) - 1.0f);
+        else
+            return x ^ tv;
+    }
+
+    // Copies the newest N words to the front of the buffer when a step of
+    // `reach` words would run past its end.
+    static __device__ __forceinline__ void maybe_compact(uint32_t *buf, uint32_t &h,
+                                                         uint32_t reach, uint32_t lane) {
+        if (h + reach > (uint32_t)BUF) {
+            for (uint32_t i = lane; i < N; i += TPS) buf[i] = buf[h - N + i];
+            group_sync<TPS>();
+            h = N;
+        }
+    }
+
+    // Steps with W < 64 on one wave: S = W outputs per step, lane l makes
+    // x_{h+l}.  Its tap x_{h+l-W} is the word it made in the previous step,
+    // so the dependent chain never leaves registers.  The next step's LDS
+    // loads are issued right after this step's word is stored, and this
+    // step's tempering and output store run while they are in flight.
+    template <bool F32, bool LIN>
+    static __device__ __forceinline__ void steps_small(const Step &p, uint32_t *__restrict__ buf,
+                                                       const uint32_t *__restrict__ tbl,
+                                                       gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                       bool want_raw, uint64_t count,
+                                                       uint32_t &h, uint64_t &done,
+                                                       uint32_t lane) {
+        const uint32_t W = p.W;
+        maybe_compact(buf, h, 64, lane);
+        uint32_t c = buf[h - W + lane];  // in bounds for every lane: h >= N > 64
+        uint32_t a = buf[h + lane - N], b = buf[h + lane - N + 1];
+        uint32_t hh = buf[h + lane - W - 1];
+        while (done < count) {
+            const uint64_t rem = count - done;
+            const uint32_t S = rem < W ? (uint32_t)rem : W;
+            uint32_t X = (a & p.mask) ^ b;
+            X ^= X << p.sh1;
+            const uint32_t x = rec<LIN>(p, tbl, X ^ (c >> p.sh2));
+            // lanes >= S write into the next step's slots, which it rewrites
+            buf[h + lane] = x;
+            const uint32_t hh_cur = hh;
+            uint32_t hn = h + S;
+            group_sync<TPS>();
+            maybe_compact(buf, hn, 64, lane);
+            a = buf[hn + lane - N];
+            b = buf[hn + lane - N + 1];
+            hh = buf[hn + lane - W - 1];
+            const uint32_t r = temper<F32>(tbl, x, hh_cur);
+            if (lane < S) {
+                gout[done + lane] = r;
+                if (want_raw) raw[N + done + lane] = x;
+            }
+            c = x;
+            h = hn;
+            done += S;
+        }
+    }
+
+    // One step of KE outputs per lane (KE = ceil(S / TPS)), straight-line.
+    template <bool F32, int KE>
+    static __device__ __forceinline__ void body(const Step &p, uint32_t *__restrict__ buf,
+                                                const uint32_t *__restrict__ tbl,
+                                                gptr<uint32_t> o, gptr<uint32_t> rw,
+                                                bool want_raw, uint32_t h, uint32_t S,
+                                                uint32_t lane) {
+        const uint32_t *q = buf + (h + lane - N);
+        const uint32_t *qp = q + (p.pos - 1);
+        uint32_t a[KE], b[KE], hh[KE], c[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            a[k] = q[k * TPS];
+            b[k] = q[k * TPS + 1];
+            hh[k] = qp[k * TPS];
+            c[k] = qp[k * TPS + 1];
+        }
+        uint32_t x[KE], r[KE];
+#pragma unroll
+        for (int k = 0; k < KE; ++k) {
+            uint32_t X = (a[k] & p.mask) ^ b[k];
+            X ^= X << p.sh1;
+            x[k] = rec<false>(p, tbl, X ^ (c[k] >> p.sh2));
+            r[k] = temper<F32>(tbl, x[k], hh[k]);
+        }
+        uint32_t *w = buf + (h + lane);
+#pragma unroll
+        for (int k = 0; k < KE; ++k) w[k * TPS] = x[k];
+        // every k but the last is full (S > (KE-1)*TPS)
+#pragma unroll
+        for (int k = 0; k < KE - 1; ++k) o[k * TPS] = r[k];
+        if (lane + (KE - 1) * TPS < S) o[(KE - 1) * TPS] = r[KE - 1];
+        if (want_raw) {
+#pragma unroll
+            for (int k = 0; k < KE; ++k)
+                if (lane + k * TPS < S) rw[k * TPS] = x[k];
+        }
+    }
+
+    template <bool F32>
+    static __device__ __forceinline__ void steps_wide(const Step &p, uint32_t *__restrict__ buf,
+                                                      const uint32_t *__restrict__ tbl,
+                                                      gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                      bool want_raw, uint64_t count,
+                                                      uint32_t &h, uint64_t &done,
+                                                      uint32_t lane) {
+        // full steps: W rounded down to whole 128-byte lines when wide
+        uint32_t smax = p.W >= 64 ? (p.W & ~31u) : p.W;
+        if (smax > (uint32_t)SMAX) smax = SMAX;
+        while (done < count) {
+            const uint64_t rem = count - done;
+            const uint32_t S = rem < smax ? (uint32_t)rem : smax;
+            // lanes compute every word of their k < keff, so keep h + SMAX
+            // inside the buffer (words past S are rewritten before any read)
+            maybe_compact(buf, h, SMAX, lane);
+            gptr<uint32_t> o = gout + done + lane;
+            gptr<uint32_t> rw = raw + N + done + lane;
+            switch ((S + TPS - 1) / TPS) {
+#define MTGP_BODY(KE) \
+    case KE: if constexpr (KE <= K) body<F32, KE>(p, buf, tbl, o, rw, want_raw, h, S, lane); break;
+                MTGP_BODY(1) MTGP_BODY(2) MTGP_BODY(3) MTGP_BODY(4)
+                MTGP_BODY(5) MTGP_BODY(6) MTGP_BODY(7) MTGP_BODY(8)
+#undef MTGP_BODY
+                default: break;
+            }
+            group_sync<TPS>();
+            h += S;
+            done += S;
+        }
+    }
 
     // Advance one stream by item.count outputs.
     template <bool F32>
@@ -70,15 +230,22 @@ struct Core {
                                                uint32_t *__restrict__ buf, uint32_t lane,
                                                uint32_t *__restrict__ err) {
         uint32_t *__restrict__ tbl = buf + BUF;
-        const uint32_t pos = prm[P_POS];
-        const uint32_t sh1 = prm[P_SH1];
-        const uint32_t sh2 = prm[P_SH2];
-        const uint32_t mask = prm[P_MASK];
-        const uint32_t W = N - pos;
+        Step p;
+        p.pos = prm[P_POS];
+        p.sh1 = prm[P_SH1];
+        p.sh2 = prm[P_SH2];
+        p.mask = prm[P_MASK];
+        p.W = N - p.pos;
+        p.rb0 = prm[P_RB + 0];
+        p.rb1 = prm[P_RB + 1];
+        p.rb2 = prm[P_RB + 2];
+        p.rb3 = prm[P_RB + 3];
+        const uint32_t lin = prm[P_LIN];
         const uint64_t count = item.count;
         const uint32_t *st_in = reinterpret_cast<const uint32_t *>(item.state_in);
         uint32_t *st_out = reinterpret_cast<uint32_t *>(item.state_out);
         gptr<uint32_t> raw = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.raw));
+        gptr<uint32_t> gout = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.out));
         const bool want_raw = (item.mode & MODE_RAW) != 0;
 
         group_sync<TPS>();  // previous user of this buffer is done with it
@@ -93,80 +260,17 @@ struct Core {
         }
         group_sync<TPS>();
 
-        // Full steps: W rounded down to whole 128-byte lines when wide.
-        uint32_t smax = W >= 64 ? (W & ~31u) : W;
-        if (smax > (uint32_t)SMAX) smax = SMAX;
         uint32_t h = N;  // buffer index of the next new word
         uint64_t done = 0;
-        gptr<uint32_t> gout = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.out));
-        while (done < count) {
-            const uint64_t rem = count - done;
-            const uint32_t S = rem < smax ? (uint32_t)rem : smax;
-            const uint32_t keff = (S + TPS - 1) / TPS;
-            // Lanes compute every word of their k < keff, so keep h + SMAX
-            // inside the buffer: loads and LDS writes of lanes beyond S then
-            // stay in bounds (their words are rewritten by the next step
-            // before anything reads them).
-            if (h + SMAX > (uint32_t)BUF) {
-                for (uint32_t i = lane; i < N; i += TPS) buf[i] = buf[h - N + i];
-                group_sync<TPS>();
-                h = N;
-            }
-            // q[0] = x_{n-N}, q[1] = x_{n-N+1}, q[pos-1] = helper, q[pos] = tap
-            const uint32_t *q = buf + (h + lane - N);
-            const uint32_t *qp = q + (pos - 1);
-            uint32_t a[K], b[K], hh[K], c[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k < (int)keff) {
-                    a[k] = q[k * TPS];
-                    b[k] = q[k * TPS + 1];
-                    hh[k] = qp[k * TPS];
-                    c[k] = qp[k * TPS + 1];
-                }
-            }
-            uint32_t x[K], r[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if (k < (int)keff) {
-                    uint32_t X = (a[k] & mask) ^ b[k];
-                    X ^= X << sh1;
-                    const uint32_t Y = X ^ (c[k] >> sh2);
-                    x[k] = Y ^ tbl[Y & 15u];
-                    uint32_t H = hh[k] ^ (hh[k] >> 16);
-                    H ^= H >> 8;
-                    const uint32_t tv = tbl[16 + (H & 15u)];
-                    if constexpr (F32)
-                        r[k] = __float_as_uint(__uint_as_float((x[k] >> 9) ^ tv) - 1.0f);
-                    else
-                        r[k] = x[k] ^ tv;
-                }
-            }
-            uint32_t *w = buf + (h + lane);
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k < (int)keff) w[k * TPS] = x[k];
-            gptr<uint32_t> o = gout + done + lane;
-            if (S == keff * TPS) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < (int)keff) __builtin_nontemporal_store(r[k], o + k * TPS);
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < (int)keff && lane + k * TPS < S)
-                        __builtin_nontemporal_store(r[k], o + k * TPS);
-            }
-            if (want_raw) {
-                gptr<uint32_t> rw = raw + N + done + lane;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (k < (int)keff && lane + k * TPS < S) rw[k * TPS] = x[k];
-            }
-            group_sync<TPS>();
-            h += S;
-            done += S;
+        if (TPS == 64 && p.W < 64) {
+            if (lin)
+                steps_small<F32, true>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
+            else
+                steps_small<F32, false>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
+        } else {
+            steps_wide<F32>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
         }
+        group_sync<TPS>();
         if (st_out != nullptr)
             for (uint32_t i = lane; i < N; i += TPS) st_out[i] = buf[h - N + i];
         if (item.mode & MODE_VERIFY) {
@@ -179,10 +283,6 @@ struct Core {
     }
 };
 
-// Generation kernel.  Each group (a wave when TPS == 64, else the workgroup)
-// takes work items until none are left.
-//  persistent != 0 : items are claimed in order through *counter.
-//  persistent == 0 : group g takes items g, g + n_groups, ...
 // Plain mode (items == nullptr): item i is stream i, advanced in place in
 // its state row by plain_count outputs written at plain_out + i*plain_count.
 struct PlainArgs {
@@ -263,18 +363,57 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
 }
 
 // Jump evaluation: out[m] = XOR over the set bits i < D of g of raw[1+i+m],
-// for m < M.  One 256-thread workgroup per item; the words are staged
-// through LDS in chunks of JUMP_CH coefficients plus the output tail, and
-// lane t owns output words m = t + 256 j of the current pass.
-constexpr int JUMP_THREADS = 256;
-constexpr int JUMP_CH = 4096;   // coefficients per LDS chunk
-constexpr int JUMP_MT = 1024;   // output words per pass (4 per lane)
+// for m < M.  One wave per item (JUMP_WAVES items per workgroup); the words
+// are staged through the wave's LDS region in chunks of JUMP_CH coefficients
+// plus the output tail, and lane l owns output words m0 + l + 64 j of the
+// current pass.
+constexpr int JUMP_WAVES = 4;
+constexpr int JUMP_CH = 2048;   // coefficients per LDS chunk
+constexpr int JUMP_JA = 8;      // output words per lane per pass
+constexpr int JUMP_MT = 64 * JUMP_JA;
 
-__global__ void __launch_bounds__(JUMP_THREADS)
+template <int JA>
+__device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ raw,
+                                          const uint32_t *__restrict__ g,
+                                          uint32_t *__restrict__ out, uint32_t D, uint32_t m0,
+                                          uint32_t mt, uint32_t *__restrict__ base,
+                                          uint32_t lane) {
+    uint32_t acc[JA];
+#pragma unroll
+    for (int j = 0; j < JA; ++j) acc[j] = 0;
+    for (uint32_t i0 = 0; i0 < D; i0 += JUMP_CH) {
+        const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
+        group_sync<64>();
+        for (uint32_t j = lane; j < ch + mt; j += 64) base[j] = raw[i0 + m0 + j];
+        group_sync<64>();
+        const uint32_t nw = (ch + 31) / 32;
+        for (uint32_t w = 0; w < nw; ++w) {
+            uint32_t bits = g[(i0 >> 5) + w];
+            if (w == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
+            while (bits) {
+                const uint32_t i = 32 * w + (uint32_t)__builtin_ctz(bits);
+                bits &= bits - 1u;
+                const uint32_t *src = base + i + lane;
+#pragma unroll
+                for (int j = 0; j < JA; ++j) acc[j] ^= src[64 * j];
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < JA; ++j) {
+        const uint32_t m = lane + 64 * j;
+        if (m < mt) out[m0 + m] = acc[j];
+    }
+}
+
+__global__ void __launch_bounds__(64 * JUMP_WAVES)
 jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
-    __shared__ uint32_t base[JUMP_CH + JUMP_MT];
-    const uint32_t t = threadIdx.x;
-    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    __shared__ uint32_t lds[JUMP_WAVES][JUMP_CH + JUMP_MT];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t *base = lds[wave];
+    for (uint32_t it = blockIdx.x * JUMP_WAVES + wave; it < n_items;
+         it += gridDim.x * JUMP_WAVES) {
         const JumpItem jit = items[it];
         const uint32_t *raw = reinterpret_cast<const uint32_t *>(jit.raw) + 1;
         const uint32_t *g = reinterpret_cast<const uint32_t *>(jit.poly);
@@ -282,29 +421,13 @@ jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
         const uint32_t D = jit.nbits, M = jit.m;
         for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
             const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
-            uint32_t acc[JUMP_MT / JUMP_THREADS] = {};
-            for (uint32_t i0 = 0; i0 < D; i0 += JUMP_CH) {
-                const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
-                __syncthreads();
-                for (uint32_t j = t; j < ch + mt; j += JUMP_THREADS) base[j] = raw[i0 + m0 + j];
-                __syncthreads();
-                const uint32_t nw = (ch + 31) / 32;
-                for (uint32_t w = 0; w < nw; ++w) {
-                    uint32_t bits = g[(i0 >> 5) + w];
-                    if (w == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
-                    while (bits) {
-                        const uint32_t i = 32 * w + (uint32_t)__builtin_ctz(bits);
-                        bits &= bits - 1u;
-#pragma unroll
-                        for (int j = 0; j < JUMP_MT / JUMP_THREADS; ++j)
-                            acc[j] ^= base[i + t + j * JUMP_THREADS];
-                    }
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < JUMP_MT / JUMP_THREADS; ++j) {
-                const uint32_t m = t + j * JUMP_THREADS;
-                if (m < mt) out[m0 + m] = acc[j];
+            switch ((mt + 63) / 64) {
+#define MTGP_JP(JA) \
+    case JA: jump_pass<JA>(raw, g, out, D, m0, mt, base, lane); break;
+                MTGP_JP(1) MTGP_JP(2) MTGP_JP(3) MTGP_JP(4)
+                MTGP_JP(5) MTGP_JP(6) MTGP_JP(7) MTGP_JP(8)
+#undef MTGP_JP
+                default: break;
             }
         }
     }
@@ -331,14 +454,16 @@ __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Store-only fill: the achievable write bandwidth next to the generator.
+// Store-only fill: the achievable write bandwidth next to the generator
+// (plain stores, as the generator uses; on gfx950 they measured faster than
+// non-temporal ones).
 __global__ void __launch_bounds__(256)
 fill_kernel(u32x4 *__restrict__ out, uint64_t n_vec, uint32_t *__restrict__ tail,
             uint32_t n_tail, uint32_t value) {
     const u32x4 v = {value, value, value, value};
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vec; i += stride)
-        __builtin_nontemporal_store(v, out + i);
+        out[i] = v;
     if (blockIdx.x == 0 && threadIdx.x < n_tail) tail[threadIdx.x] = value;
 }
 
@@ -430,11 +555,11 @@ hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs
 
 hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
-    int grid = (int)n_items;
-    const int cap = num_cus * 8;
+    int grid = (int)((n_items + JUMP_WAVES - 1) / JUMP_WAVES);
+    const int cap = num_cus * 4;  // 4 blocks of 40 KB LDS fill a CU
     if (grid > cap) grid = cap;
     (void)hipGetLastError();  // report this launch only
-    hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(JUMP_THREADS), 0, s, items, n_items);
+    hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(64 * JUMP_WAVES), 0, s, items, n_items);
     return hipGetLastError();
 }
 

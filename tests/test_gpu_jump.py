@@ -65,7 +65,7 @@ def test_split_batch_matches_oracle(torch, mexp, count):
     N = mexp // 32 + 1
     counts = [count, count // 2 + 7, count, 3 * count // 4 + 1, 1000, count]
     dts = [0, 1, 0, 1, 0, 1]
-    with _Tune(mexp, 64):
+    with _Tune(mexp, 256):
         g = mtgp.Generators(p, seeds)
         outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in counts]
         items = [(k, dts[k], counts[k], outs[k]) for k in range(6)]
