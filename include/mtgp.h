@@ -70,8 +70,10 @@ enum {
 
 enum { MTGP_U32 = 0, MTGP_F32 = 1 };
 
-/* Bytes of device memory one stream's parameter block takes (256). */
-#define MTGP_DEVICE_PARAM_BYTES 256
+/* Bytes of device memory one stream's parameter block takes (4096): the
+ * parameters plus derived data (for linear recursion tables with a short
+ * step width, the 32x32 GF(2) matrix powers the windowed path uses). */
+#define MTGP_DEVICE_PARAM_BYTES 4096
 
 /* N = floor(mexp/32)+1 for a supported mexp, else MTGP_EINVAL. */
 int mtgp_state_words(uint32_t mexp);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -116,6 +117,67 @@ std::shared_ptr<ParamSet> lookup_params(const void *d_params, int n_streams) {
     return it->second;
 }
 
+// 32x32 matrices over GF(2) as column words: m[j] = M e_j.
+using Mat32 = std::array<uint32_t, 32>;
+
+static uint32_t mat_vec(const Mat32 &m, uint32_t v) {
+    uint32_t r = 0;
+    for (int j = 0; j < 32; ++j)
+        if ((v >> j) & 1u) r ^= m[j];
+    return r;
+}
+
+static Mat32 mat_mul(const Mat32 &a, const Mat32 &b) {
+    Mat32 c;
+    for (int j = 0; j < 32; ++j) c[j] = mat_vec(a, b[j]);
+    return c;
+}
+
+static Mat32 mat_pow(Mat32 m, uint64_t e) {
+    Mat32 r;
+    for (int j = 0; j < 32; ++j) r[j] = 1u << j;
+    while (e) {
+        if (e & 1u) r = mat_mul(r, m);
+        m = mat_mul(m, m);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Windowed small-step data for a linear recursion table and W < 64: the
+// tap chain x_n = G(X_n) ^ M x_{n-W}, with G(y) = y ^ rec[y & 15] and
+// M y = G(y >> sh2), is split across q = 64/W lanes per residue class with
+// E elements per lane; lanes are stitched by a scan with M^(E*2^r).
+static void window_data(const mtgp_params &p, int N, uint32_t *b) {
+    const uint32_t W = (uint32_t)N - p.pos;
+    const uint32_t q = 64u / W;
+    const uint32_t wn = std::min<uint32_t>((uint32_t)N - 1, W * q * (uint32_t)WIN_EMAX);
+    const uint32_t per_class = (wn + W - 1) / W;
+    const uint32_t E = (per_class + q - 1) / q;
+    uint32_t rounds = 0;
+    while ((1u << rounds) < q) ++rounds;
+    b[P_WIN_WN] = wn;
+    b[P_WIN_E] = E;
+    b[P_WIN_Q] = q;
+    b[P_WIN_ROUNDS] = rounds;
+    Mat32 M;
+    for (int j = 0; j < 32; ++j) {
+        if ((uint32_t)j < p.sh2) {
+            M[j] = 0;
+            continue;
+        }
+        const uint32_t y = 1u << (j - p.sh2);
+        M[j] = y ^ p.rec_tbl[y & 15u];
+    }
+    Mat32 P = mat_pow(M, E);
+    for (uint32_t r = 0; r < rounds; ++r) {
+        uint32_t *t = b + P_WIN_MAT + r * WIN_MAT_WORDS;
+        for (int k = 0; k < 8; ++k)
+            for (uint32_t v = 0; v < 16; ++v) t[k * 16 + v] = mat_vec(P, v << (4 * k));
+        P = mat_mul(P, P);
+    }
+}
+
 static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, void *d_params,
                          hipStream_t s) {
     int rc = check_params(h, n);
@@ -149,6 +211,7 @@ static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, voi
         }
         b[P_LIN] = lin ? 1u : 0u;
         for (int bit = 0; bit < 4; ++bit) b[P_RB + bit] = h[k].rec_tbl[1 << bit];
+        if (lin && (uint32_t)N - h[k].pos < 64u) window_data(h[k], N, b);
         std::memcpy(b + P_REC, h[k].rec_tbl, 64);
         std::memcpy(b + P_TMP, h[k].tmp_tbl, 64);
         std::memcpy(b + P_FLT, h[k].flt_tbl, 64);

@@ -7,7 +7,7 @@
 
 namespace mtgp {
 
-// Device parameter block: 64 words (256 bytes) per stream.
+// Device parameter block: 1024 words (4 KB) per stream.
 enum : uint32_t {
     P_MEXP = 0,
     P_N = 1,
@@ -22,8 +22,17 @@ enum : uint32_t {
     P_REC = 16,
     P_TMP = 32,
     P_FLT = 48,
-    P_WORDS = 64,
+    // windowed small-step path (linear recursion table, W < 64)
+    P_WIN_WN = 64,       // window length (<= N-1)
+    P_WIN_E = 65,        // elements per lane and window
+    P_WIN_Q = 66,        // lanes per residue class (64 / W)
+    P_WIN_ROUNDS = 67,   // cross-lane scan rounds, ceil(log2 q)
+    P_WIN_MAT = 128,     // nibble tables of M^(E*2^r): [round][nibble][16]
+    P_WORDS = 1024,      // 4 KB per stream
 };
+constexpr int WIN_EMAX = 16;
+constexpr int WIN_MAXROUNDS = 5;
+constexpr int WIN_MAT_WORDS = 128;   // 8 nibbles x 16 entries
 
 // BatchItem.mode bits
 enum : uint32_t {

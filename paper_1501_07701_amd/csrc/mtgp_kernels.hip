@@ -62,7 +62,11 @@ struct Core {
     static constexpr int BUF = buf_words(N, SMAX);
     static_assert(BUF >= 2 * N + SMAX, "compaction would overlap");
     static_assert(N > 64, "the small-step path assumes N > 64");
-    static constexpr int LDS_WORDS = BUF + 32;  // + recursion and output tables
+    // LDS per group: the state buffer, the recursion and output tables, a
+    // 64-word exchange area and the window path's scan matrices.
+    static constexpr int SCR = BUF + 32;
+    static constexpr int MATS = SCR + 64;
+    static constexpr int LDS_WORDS = MATS + WIN_MAXROUNDS * WIN_MAT_WORDS;
 
     struct Step {  // per-item values, uniform across the group
         uint32_t pos, sh1, sh2, mask, W;
@@ -99,7 +103,11 @@ struct Core {
     }
 
     // Copies the newest N words to the front of the buffer when a step of
-    // `reach` words would run past its end.
+    // `reach` words would run past its end.  With several waves the source
+    // [h-N, h) and destination [0, N) never overlap (h > BUF - SMAX >= 2N);
+    // a single wave may also copy with overlap (the window path), which is
+    // safe because its LDS reads and writes execute in instruction order and
+    // the copy moves words towards lower addresses.
     static __device__ __forceinline__ void maybe_compact(uint32_t *buf, uint32_t &h,
                                                          uint32_t reach, uint32_t lane) {
         if (h + reach > (uint32_t)BUF) {
@@ -149,6 +157,116 @@ struct Core {
             c = x;
             h = hn;
             done += S;
+        }
+    }
+
+    // y = P v for a 32x32 GF(2) matrix given as 8 nibble tables of 16 words.
+    static __device__ __forceinline__ uint32_t mat_apply(const uint32_t *t, uint32_t v) {
+        uint32_t y = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) y ^= t[k * 16 + ((v >> (4 * k)) & 15u)];
+        return y;
+    }
+
+    // Windowed steps for W < 64 with a linear recursion table, one wave.
+    // A window of Wn <= N-1 words only reads words older than its start for
+    // x_{n-N} and x_{n-N+1}, so all of them are loaded first.  What remains
+    // is the tap chain x_n = G(X_n) ^ M x_{n-W} per residue class n mod W,
+    // which is affine: class r is cut into q chunks of E elements (one lane
+    // each); every lane runs its chunk from a zero carry, a Hillis-Steele
+    // scan with M^(E*2^k) gives each lane its true carry, and the lane
+    // reruns its chunk from it.  Tempering and stores then run as one
+    // coalesced pass over the window.
+    template <bool F32>
+    static __device__ __forceinline__ void steps_window(const Step &p,
+                                                        const uint32_t *__restrict__ prm,
+                                                        uint32_t *__restrict__ buf,
+                                                        const uint32_t *__restrict__ tbl,
+                                                        gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                        bool want_raw, uint64_t count,
+                                                        uint32_t &h, uint64_t &done,
+                                                        uint32_t lane) {
+        uint32_t *scr = buf + (SCR - 0);
+        uint32_t *mats = buf + MATS;
+        const uint32_t W = p.W;
+        const uint32_t wn = prm[P_WIN_WN], E = prm[P_WIN_E], q = prm[P_WIN_Q];
+        const uint32_t rounds = prm[P_WIN_ROUNDS];
+        for (uint32_t i = lane; i < rounds * WIN_MAT_WORDS; i += 64) mats[i] = prm[P_WIN_MAT + i];
+        const uint32_t r = lane / q, sub = lane - (lane / q) * q;
+        const bool lane_ok = r < W;
+        const uint32_t i0 = sub * E;
+        group_sync<TPS>();
+        while (done < count) {
+            const uint64_t rem = count - done;
+            const uint32_t wc = rem < wn ? (uint32_t)rem : wn;
+            maybe_compact(buf, h, wn + 64, lane);
+            // this lane's elements: class r, indices i0 .. i0+cnt-1
+            const uint32_t lr = (lane_ok && wc > r) ? (wc - 1 - r) / W + 1 : 0u;
+            const uint32_t cnt = lr > i0 ? (lr - i0 < E ? lr - i0 : E) : 0u;
+            uint32_t X[WIN_EMAX];
+#pragma unroll
+            for (int j = 0; j < WIN_EMAX; ++j) {
+                if (j < (int)E) {
+                    const uint32_t pp = r + W * (i0 + j);
+                    const uint32_t idx = ((uint32_t)j < cnt) ? h + pp - N : h - N;
+                    const uint32_t a = buf[idx], b = buf[idx + 1];
+                    const uint32_t x0 = (a & p.mask) ^ b;
+                    X[j] = x0 ^ (x0 << p.sh1);
+                }
+            }
+            // chunk from a zero carry (the first chunk of a class from its
+            // true carry, the class's last word before the window)
+            uint32_t c = (sub == 0 && lane_ok) ? buf[h + r - W] : 0u;
+            uint32_t v[WIN_EMAX];
+            uint32_t last = 0;
+#pragma unroll
+            for (int j = 0; j < WIN_EMAX; ++j) {
+                if (j < (int)E) {
+                    c = rec<true>(p, tbl, X[j] ^ (c >> p.sh2));
+                    v[j] = c;
+                    last = c;
+                }
+            }
+            if (rounds) {
+                // u_s <- u_s ^ M^(E*d) u_{s-d}: true last word of each chunk
+                uint32_t u = last;
+                for (uint32_t k = 0; k < rounds; ++k) {
+                    const uint32_t d = 1u << k;
+                    scr[lane] = u;
+                    group_sync<TPS>();
+                    const uint32_t w = scr[sub >= d ? lane - d : lane];
+                    group_sync<TPS>();
+                    if (sub >= d) u ^= mat_apply(mats + k * WIN_MAT_WORDS, w);
+                }
+                scr[lane] = u;
+                group_sync<TPS>();
+                const uint32_t cin = scr[sub > 0 ? lane - 1 : lane];
+                group_sync<TPS>();
+                if (sub > 0) {
+                    c = cin;
+#pragma unroll
+                    for (int j = 0; j < WIN_EMAX; ++j) {
+                        if (j < (int)E) {
+                            c = rec<true>(p, tbl, X[j] ^ (c >> p.sh2));
+                            v[j] = c;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < WIN_EMAX; ++j)
+                if (j < (int)E && (uint32_t)j < cnt) buf[h + r + W * (i0 + j)] = v[j];
+            group_sync<TPS>();
+            // tempering and stores, coalesced over the window
+            for (uint32_t pp = lane; pp < wc; pp += 64) {
+                const uint32_t x = buf[h + pp];
+                const uint32_t hh = buf[h + pp - W - 1];
+                gout[done + pp] = temper<F32>(tbl, x, hh);
+                if (want_raw) raw[N + done + pp] = x;
+            }
+            group_sync<TPS>();
+            h += wc;
+            done += wc;
         }
     }
 
@@ -264,7 +382,7 @@ struct Core {
         uint64_t done = 0;
         if (TPS == 64 && p.W < 64) {
             if (lin)
-                steps_small<F32, true>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
+                steps_window<F32>(p, prm, buf, tbl, gout, raw, want_raw, count, h, done, lane);
             else
                 steps_small<F32, false>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
         } else {

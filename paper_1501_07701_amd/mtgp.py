@@ -20,7 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libmtgp.so")
 PARAM_WORDS = 53
-DEVICE_PARAM_BYTES = 256
+DEVICE_PARAM_BYTES = 4096
 U32, F32 = 0, 1
 PENDING, DONE, FAILED = 0, 1, 2
 

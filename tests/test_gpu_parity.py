@@ -92,6 +92,50 @@ def test_plain_ragged_calls_all_mexp(torch, mexp):
     g.close()
 
 
+@pytest.mark.parametrize("mexp", [3217, 23209])
+def test_nonlinear_recursion_tables(torch, mexp):
+    """Tables that are not GF(2) spans take the table-lookup paths (the
+    windowed small-step path needs a linear recursion table)."""
+    _say("case nonlinear tables mexp=%d" % mexp)
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 6, 0x4E4C + mexp)
+    rng = np.random.default_rng(mexp)
+    p[:, 5:21] = rng.integers(0, 2**32, (6, 16), dtype=np.uint64).astype(np.uint32)
+    p[0, 1], p[1, 1], p[2, 1] = N - 2, N - 40, 1      # W = 2, 40, N-1
+    seeds = np.arange(1, 7, dtype=np.uint32)
+    g = mtgp.Generators(p, seeds)
+    a = _host(g.generate(9000, mtgp.U32)).reshape(6, 9000)
+    b = _host(g.generate(777, mtgp.F32)).reshape(6, 777)
+    exp, exp_states = _oracle_run(p, seeds, [9000, 777], [False, True])
+    for k in range(6):
+        assert np.array_equal(a[k], exp[k][0]), k
+        assert np.array_equal(b[k], exp[k][1]), k
+    assert np.array_equal(g.states_host(), exp_states)
+    g.close()
+
+
+@pytest.mark.parametrize("w", [2, 3, 5, 16, 21, 31, 32, 33, 63])
+def test_every_short_step_width(torch, w):
+    """The windowed path for each lanes-per-class split (q = 64 // W)."""
+    _say("case short W=%d" % w)
+    for mexp in (11213, 44497):
+        N = mexp // 32 + 1
+        p = workloads.make_params(mexp, 3, 0x5757 + w)
+        p[:, 1] = N - w
+        p[1, 3] = 0                                      # sh2 = 0
+        p[2, 2], p[2, 3] = 31, 31
+        seeds = np.array([0, 7, 0xFFFFFFFF], dtype=np.uint32)
+        g = mtgp.Generators(p, seeds)
+        calls = [1, w - 1 if w > 1 else 1, 5 * N + 3, 2 * N]
+        got = [_host(g.generate(c, mtgp.U32)).reshape(3, c) for c in calls]
+        exp, exp_states = _oracle_run(p, seeds, calls, [False] * len(calls))
+        for k in range(3):
+            for i in range(len(calls)):
+                assert np.array_equal(got[i][k], exp[k][i]), (mexp, k, i)
+        assert np.array_equal(g.states_host(), exp_states)
+        g.close()
+
+
 @pytest.mark.parametrize("mexp", [11213, 44497])
 def test_every_compiled_tuning_gives_identical_output(torch, mexp):
     _say("case tunings mexp=%d" % mexp)
