@@ -1,12 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of bulk MTGP32 generation on one MI355X.
 
-One step = the whole hot path over one batch of the 128-stream mexp-11213
-workload: re-seed every stream from its seed status on the device, generate
-2^24 uint32 outputs per stream, re-seed, generate 2^24 float32 outputs per
-stream from the same initial states (both passes through the persistent
-batch kernel replayed from a hipGraph).  Inputs (parameter blocks, seeds)
-are resident in HBM before timing starts.
+Default workload (the headline line): one step = the whole hot path over
+one batch of the 128-stream mexp-11213 workload: re-seed every stream from
+its seed status on the device, generate 2^24 uint32 outputs per stream,
+re-seed, generate 2^24 float32 outputs per stream from the same initial
+states (both passes through the persistent batch kernel replayed from a
+hipGraph).  Inputs (parameter blocks, seeds) are resident in HBM before
+timing starts.
+
+--workload selects the scheduler and serving measurements instead:
+  C3  4096 mexp-23209 streams x 2^20 uint32 in one autotuned graph launch
+  C4  1024 mexp-44497 streams, lengths log-uniform in [2^10, 2^24], mixed
+      dtype, one launch, against one launch per stream in order
+  C5  serving: 16384 resident mexp-11213 streams, Poisson request traces at
+      fractions of the saturation rate, against one launch per request
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -57,29 +65,11 @@ def cpu_baseline(params, seeds, count, threads):
     return n_out / dt / 1e9, dt
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the CPU oracle leg (profiling runs)")
-    ap.add_argument("--calibrate", action="store_true",
-                    help="also run a store-only fill and a copy of known size, "
-                         "the references for hardware counter scaling")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: the streams are independent and a "
-              "multi-GPU run would only shard them (no communication); "
-              "--gpus %d is not supported in this build" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
+def run_c2(args):
     import numpy as np
     import torch
     from paper_1501_07701_amd import mtgp, workloads
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
     cfg = workloads.CONFIGS["C2"]
     params, seeds = workloads.config_inputs("C2")
     n, count, mexp = params.shape[0], cfg["count"], cfg["mexp"]
@@ -209,6 +199,408 @@ def main():
                        "plan_build_s": round(t_plan, 3),
                        "segment_check_failures": seg_errors},
     }
+    return line
+
+
+
+
+def cpu_sample(params, seeds, counts, dtypes, threads):
+    """The CPU oracle, as it stands, on a bounded sample: stream k generates
+    counts[k] outputs of dtype dtypes[k] from its seeded state; streams are
+    spread over a thread pool and outputs dropped as each call returns.
+    Returns (G outputs/s, seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    N = int(params[0, 0]) // 32 + 1
+
+    def one(k):
+        st = oracle.seed(int(seeds[k]), N)
+        oracle.generate(params[k], st, int(counts[k]), bool(dtypes[k]))
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(params.shape[0])))
+    dt = time.perf_counter() - t0
+    return float(sum(int(c) for c in counts)) / dt / 1e9, dt
+
+
+def _threads():
+    return min(16, len(os.sched_getaffinity(0)))
+
+
+def _timed_steps(torch, step, warmup, steps):
+    """Runs warmup untimed steps, then `steps` timed ones; step(record)
+    returns (e0, e1) event pairs to average when record is true."""
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    pairs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pairs += step(True)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    launch = [a.elapsed_time(b) for a, b in pairs]
+    return ms_per_step, sum(launch) / len(launch)
+
+
+def _pair(torch, stream):
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    return e0, e1
+
+
+def _fill_gbps(torch, mtgp, out, stream):
+    ms = []
+    for _ in range(3):
+        e0, e1 = _pair(torch, stream)
+        mtgp.fill_u32(out, out.numel(), 0)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    return out.numel() * 4 / (min(ms) * 1e-3) / 1e9
+
+
+def _common(args, value, unit, ms_per_step, config, achieved, cpu, extra):
+    line = {
+        "metric": "G uint32/s and % HBM write roofline",
+        "value": round(value, 3),
+        "unit": unit,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: seeded random MTGP32 parameter sets, seeds k+1",
+        "config": config,
+        "roofline": None if achieved is None else {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    line.update(extra)
+    return line
+
+
+def run_c3(args):
+    """4096 streams x 2^20 uint32 (mexp 23209) in one graph launch, after
+    the autotuner picked the launch shape and jump-ahead target."""
+    import numpy as np
+    import torch
+    from paper_1501_07701_amd import mtgp, workloads
+
+    cfg = workloads.CONFIGS["C3"]
+    params, seeds = workloads.config_inputs("C3")
+    n, count, mexp = params.shape[0], cfg["count"], cfg["mexp"]
+    N = mtgp.state_words(mexp)
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    items = [(k, mtgp.U32, count, out.data_ptr() + 4 * k * count) for k in range(n)]
+    arr = mtgp.make_work(items)
+    stream = torch.cuda.current_stream()
+    log("autotune ...")
+    t0 = time.perf_counter()
+    st_bytes = (n * g.stride * 4 + 255) // 256 * 256
+    scratch = torch.empty(st_bytes + 4 * mtgp.batch_workspace_query(g.d_params, items),
+                          dtype=torch.uint8, device="cuda")
+    best, cand_ms = mtgp.autotune(g.d_params, g.d_states, g.stride, items, scratch, reps=2)
+    t_tune = time.perf_counter() - t0
+    del scratch
+    ws = g.workspace(items)
+
+    def step(record):
+        g.reseed()
+        pr = _pair(torch, stream) if record else None
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, arr, ws)
+        if record:
+            pr[1].record(stream)
+            return [pr]
+        return []
+
+    log("timing ...")
+    ms_step, ms_launch = _timed_steps(torch, step, args.warmup, args.steps)
+    if mtgp.batch_errors(ws):
+        log("jump-ahead segment checks failed")
+        sys.exit(3)
+    fill = _fill_gbps(torch, mtgp, out, stream)
+    alg = n * count * 4 + n * (8 * N + 256)
+    cpu = None
+    if not args.no_cpu_baseline:
+        th, c = _threads(), 1 << 19
+        log("cpu baseline ...")
+        cv, dt = cpu_sample(params, seeds, [c] * n, [0] * n, th)
+        cpu = {"value": round(cv, 4), "unit": "G uint32/s", "cores": th, "kind": "oracle",
+               "sample": "all 4096 streams x 2^19 uint32 outputs from the seeded states, "
+                         "%.2f s wall on %d threads" % (dt, th)}
+    W = N - params[:, 1].astype(np.int64)
+    cands = mtgp.tuning_candidates(mexp)
+    return _common(args, n * count / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
+                   {"workload": cfg["name"], "mexp": mexp, "streams": n,
+                    "outputs_per_stream": count, "passes": ["u32"]},
+                   alg / (ms_launch * 1e-3) / 1e9, cpu,
+                   {"avg_generate_launch_ms": round(ms_launch, 3),
+                    "store_only_fill_GBps": round(fill, 1),
+                    "autotuned": {"threads_per_stream": best.threads_per_stream,
+                                  "outputs_per_lane": best.outputs_per_lane,
+                                  "workgroup_size": best.workgroup_size,
+                                  "jump_target_steps": best.jump_target_steps,
+                                  "tune_s": round(t_tune, 2),
+                                  "candidate_ms": {"%d/%d/%d" % c.as_tuple()[:3]:
+                                                   round(m, 3) for c, m in
+                                                   zip(cands, cand_ms)}},
+                    "min_step_width": int(W.min())})
+
+
+def run_c4(args):
+    """1024 streams of mexp 44497 with log-uniform lengths and mixed dtype in
+    one batch launch, against one launch per stream in stream order on one
+    HIP stream (with and without jump-ahead splitting)."""
+    import numpy as np
+    import torch
+    from paper_1501_07701_amd import mtgp, workloads
+
+    cfg = workloads.CONFIGS["C4"]
+    params, seeds = workloads.config_inputs("C4")
+    lengths, dtypes = workloads.uneven_batch("C4")
+    n, mexp = params.shape[0], cfg["mexp"]
+    N = mtgp.state_words(mexp)
+    total = int(lengths.sum())
+    offs = np.concatenate([[0], np.cumsum(lengths.astype(np.int64))[:-1]])
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    base = out.data_ptr()
+    items = [(k, int(dtypes[k]), int(lengths[k]), base + 4 * int(offs[k])) for k in range(n)]
+    arr = mtgp.make_work(items)
+    ws = g.workspace(items)
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        g.reseed()
+        pr = _pair(torch, stream) if record else None
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, arr, ws)
+        if record:
+            pr[1].record(stream)
+            return [pr]
+        return []
+
+    log("timing batch ...")
+    ms_step, ms_launch = _timed_steps(torch, step, args.warmup, args.steps)
+    if mtgp.batch_errors(ws):
+        log("jump-ahead segment checks failed")
+        sys.exit(3)
+
+    # one launch per stream, in order
+    def per_stream(split):
+        t = mtgp.get_tuning(mexp)
+        tt = t.as_tuple()
+        if not split:
+            mtgp.set_tuning(mexp, tt[0], tt[1], tt[2], 0)
+        try:
+            one = [mtgp.make_work([it]) for it in items]
+            wsz = max(mtgp.batch_workspace_query(g.d_params, [it]) for it in items)
+            w1 = torch.empty(wsz, dtype=torch.uint8, device="cuda")
+            g.reseed()
+            torch.cuda.synchronize()
+            e0, e1 = _pair(torch, stream)
+            t0 = time.perf_counter()
+            for a in one:
+                mtgp.generate_batch(g.d_params, g.d_states, g.stride, a, w1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            bad = mtgp.batch_errors(w1)
+            return wall, e0.elapsed_time(e1), bad
+        finally:
+            mtgp.set_tuning(mexp, *tt)
+
+    log("one launch per stream, jump-ahead on ...")
+    b_split = per_stream(True)
+    log("one launch per stream, jump-ahead off ...")
+    b_plain = per_stream(False)
+    if b_split[2] or b_plain[2]:
+        log("jump-ahead segment checks failed in the per-stream runs")
+        sys.exit(3)
+    fill = _fill_gbps(torch, mtgp, out, stream)
+    alg = total * 4 + n * (8 * N + 256)
+    cpu = None
+    if not args.no_cpu_baseline:
+        th = _threads()
+        cnt = np.minimum(lengths, 1 << 21)
+        log("cpu baseline ...")
+        cv, dt = cpu_sample(params, seeds, cnt, dtypes, th)
+        cpu = {"value": round(cv, 4), "unit": "G uint32/s", "cores": th, "kind": "oracle",
+               "sample": "all 1024 streams, the first min(L, 2^21) outputs of each in "
+                         "its dtype, from the seeded states, %.2f s wall on %d threads"
+                         % (dt, th)}
+    return _common(args, total / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
+                   {"workload": cfg["name"], "mexp": mexp, "streams": n,
+                    "total_outputs": total, "f32_fraction": round(float(dtypes.mean()), 3)},
+                   alg / (ms_launch * 1e-3) / 1e9, cpu,
+                   {"avg_generate_launch_ms": round(ms_launch, 3),
+                    "store_only_fill_GBps": round(fill, 1),
+                    "one_launch_per_stream": {
+                        "jump_ahead_ms": round(b_split[0], 2),
+                        "unsplit_ms": round(b_plain[0], 2),
+                        "speedup_of_batch_vs_jump_ahead": round(b_split[0] / ms_step, 2),
+                        "speedup_of_batch_vs_unsplit": round(b_plain[0] / ms_step, 2)}})
+
+
+def _serve(mtgp, srv, trace, n, scale):
+    """Submits the first n requests of `trace` at their arrival times
+    (t_arrival * scale seconds after the start) and collects them.
+    Returns (latency ns per request, completion ns per request)."""
+    import numpy as np
+    arr_ns = trace["t_arrival"][:n] * scale * 1e9
+    st, L, dt = trace["stream"], trace["length"], trace["dtype"]
+    lat = np.zeros(n)
+    fin = np.zeros(n)
+    waiting = []
+    i = done = 0
+    t0 = time.monotonic_ns()
+    last_scan = -10**9
+    while done < n:
+        now = time.monotonic_ns() - t0
+        while i < n and arr_ns[i] <= now:
+            try:
+                tk = srv.submit(int(st[i]), int(L[i]), int(dt[i]))
+            except mtgp.MTGPError as e:
+                if e.code != mtgp.EAGAIN:
+                    raise
+                break
+            waiting.append((tk, i))
+            i += 1
+        if now - last_scan > 1_000_000 or i >= n:
+            keep = []
+            for tk, j in waiting:
+                s, _ = srv.poll(tk)
+                if s == mtgp.PENDING:
+                    keep.append((tk, j))
+                    continue
+                if s != mtgp.DONE:
+                    raise RuntimeError("request %d failed" % j)
+                td = srv.times(tk)[3]
+                lat[j] = td - (t0 + arr_ns[j])
+                fin[j] = td - t0
+                srv.release(tk)
+                done += 1
+            waiting = keep
+            last_scan = now
+        nxt = (arr_ns[i] - (time.monotonic_ns() - t0)) * 1e-9 if i < n else 2e-4
+        time.sleep(min(max(nxt, 0.0), 2e-4))
+    return lat, fin
+
+
+def run_c5(args):
+    """Serving: 16384 resident mexp-11213 streams; Poisson arrivals of
+    requests with log-uniform lengths in [2^8, 2^24] and mixed dtype at
+    fractions of the saturation rate; p50/p99 latency (arrival to the
+    server's completion stamp) against one launch per request served FIFO
+    on one HIP stream."""
+    import numpy as np
+    import torch
+    from paper_1501_07701_amd import mtgp, workloads
+
+    cfg = workloads.CONFIGS["C5"]
+    params, seeds = workloads.config_inputs("C5")
+    n_streams, mexp = params.shape[0], cfg["mexp"]
+    n_req = args.requests
+    g = mtgp.Generators(params, seeds)
+    lo, hi = cfg["len_log2"]
+    trace = workloads.request_trace(n_req, 1.0, n_streams, len_log2=(lo, hi),
+                                    p_float=cfg["p_float"], master=cfg["master"])
+    mean_L = float(trace["length"].mean())
+    srv = mtgp.Server(g, cfg["pool_bytes"], inflight=4, max_batch_items=512,
+                      batch_window_ns=50_000, workspace_bytes_per_batch=128 << 20)
+    try:
+        # saturation: every request arrives at once (also builds the
+        # jump-ahead data of the streams the trace touches)
+        log("saturation run ...")
+        _, fin = _serve(mtgp, srv, trace, n_req, 0.0)
+        log("saturation run 2 ...")
+        _, fin = _serve(mtgp, srv, trace, n_req, 0.0)
+        sat_outputs_s = float(trace["length"][:n_req].sum()) / (fin.max() * 1e-9)
+        lam_sat = sat_outputs_s / mean_L
+        rates = []
+        for f in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
+            lam = f * lam_sat
+            log("rate %.2f x saturation (%.0f req/s) ..." % (f, lam))
+            lat, fin = _serve(mtgp, srv, trace, n_req, 1.0 / lam)
+            rates.append({"frac": f, "req_per_s": round(lam, 1),
+                          "p50_ms": round(float(np.percentile(lat, 50)) * 1e-6, 3),
+                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
+                          "served_G_per_s": round(float(trace["length"][:n_req].sum())
+                                                  / (fin.max() * 1e-9) / 1e9, 3)})
+    finally:
+        srv.close()
+
+    # one launch per request, FIFO on one HIP stream: each request's
+    # service time measured alone (host planning + launch + completion),
+    # then queued at the same arrival times
+    log("one launch per request ...")
+    nb = min(n_req, 1000)
+    buf = torch.empty(int(trace["length"][:nb].max()), dtype=torch.int32, device="cuda")
+    w1 = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    d = np.zeros(nb)
+    for i in range(nb):
+        it = [(int(trace["stream"][i]), int(trace["dtype"][i]), int(trace["length"][i]),
+               buf.data_ptr())]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, it, w1)
+        torch.cuda.synchronize()
+        d[i] = time.perf_counter() - t0
+    base_outputs_s = float(trace["length"][:nb].sum()) / d.sum()
+    for r in rates:
+        arr = trace["t_arrival"][:nb] / r["req_per_s"]
+        fin_t = np.zeros(nb)
+        t = 0.0
+        for i in range(nb):
+            t = max(t, arr[i]) + d[i]
+            fin_t[i] = t
+        lat = fin_t - arr
+        r["one_launch_per_request_p50_ms"] = round(float(np.percentile(lat, 50)) * 1e3, 3)
+        r["one_launch_per_request_p99_ms"] = round(float(np.percentile(lat, 99)) * 1e3, 3)
+    line = _common(args, sat_outputs_s / 1e9, "G outputs/s", 0.0,
+                   {"workload": cfg["name"], "mexp": mexp, "resident_streams": n_streams,
+                    "requests_per_rate": n_req, "mean_request_outputs": round(mean_L)},
+                   None, None,
+                   {"saturation_req_per_s": round(lam_sat, 1),
+                    "one_launch_per_request_G_per_s": round(base_outputs_s / 1e9, 3),
+                    "rates": rates})
+    line["metric"] = "served G outputs/s at saturation; p50/p99 latency per arrival rate"
+    line["steps"] = 0
+    line["warmup"] = 0
+    return line
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5"])
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="C5: requests per arrival rate")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a store-only fill and a copy of known size, "
+                         "the references for hardware counter scaling")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the streams are independent and a "
+              "multi-GPU run would only shard them (no communication); "
+              "--gpus %d is not supported in this build" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    run = {"C2": run_c2, "C3": run_c3, "C4": run_c4, "C5": run_c5}[args.workload]
+    line = run(args)
     print(json.dumps(line), flush=True)
 
 

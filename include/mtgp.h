@@ -196,7 +196,7 @@ int mtgp_tuning_candidates(uint32_t mexp, mtgp_tuning *out, int max_out);
 
 /* Autotuner: times every compiled launch candidate on the given batch (run
  * on a scratch copy of the states, so the caller's states are untouched),
- * then the jump-ahead target steps in {0, 1024, 4096, 16384, 65536} with the
+ * then the jump-ahead target steps in {0, 1024, 2048, 4096, 8192, 16384, 65536} with the
  * fastest candidate, keeps the fastest combination as the tuning for this
  * mexp and returns it in *best.  d_scratch holds n_streams * state_stride * 4
  * bytes (rounded up to 256) followed by the batch workspace;

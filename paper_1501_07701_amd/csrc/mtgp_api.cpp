@@ -190,6 +190,7 @@ static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, voi
     set->N = N;
     set->mexp = h[0].mexp;
     set->W.resize(n);
+    set->lin.resize(n);
     for (int k = 0; k < n; ++k) {
         uint32_t *b = &blob[(size_t)k * P_WORDS];
         b[P_MEXP] = h[k].mexp;
@@ -216,6 +217,7 @@ static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, voi
         std::memcpy(b + P_TMP, h[k].tmp_tbl, 64);
         std::memcpy(b + P_FLT, h[k].flt_tbl, 64);
         set->W[k] = (uint32_t)N - h[k].pos;
+        set->lin[k] = lin ? 1 : 0;
     }
     hipError_t e = hipMemcpyAsync(d_params, blob.data(), blob.size() * 4,
                                   hipMemcpyHostToDevice, s);
@@ -237,12 +239,12 @@ static std::map<int, mtgp_tuning> g_tune;  // keyed by N
 static mtgp_tuning default_tuning(int N) {
     // One wave per stream, 4 waves per workgroup; K sized so a step can
     // cover the typical step width W (uniform in [2, N-1]); streams needing
-    // more than 4096 dependent steps are split by jump-ahead.
+    // more than 2048 dependent steps are split by jump-ahead.
     mtgp_tuning t;
     t.threads_per_stream = 64;
     t.workgroup_size = 256;
     t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 4 : 8);
-    t.jump_target_steps = 4096;
+    t.jump_target_steps = 2048;
     return t;
 }
 

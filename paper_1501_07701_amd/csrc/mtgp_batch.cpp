@@ -77,9 +77,17 @@ static uint64_t pow2ceil(uint64_t v) {
     return p;
 }
 
-uint64_t step_outputs(uint32_t W, const mtgp_tuning &t) {
-    uint64_t s = W >= 64 ? (W & ~31u) : W;
+// Cost model: outputs a stream yields per dependent step of the wide path
+// (one LDS round trip).  Narrow streams with a linear rec_tbl run the
+// windowed scan instead, which measures at about 40 + W/2 outputs per
+// wide-step time whatever W is.
+uint64_t step_outputs(const ParamSet &ps, int stream, const mtgp_tuning &t) {
+    const uint32_t W = ps.W[(size_t)stream];
     const uint64_t smax = (uint64_t)t.threads_per_stream * (uint64_t)t.outputs_per_lane;
+    uint64_t s;
+    if (W >= 64) s = W & ~31u;
+    else if (t.threads_per_stream == 64 && ps.lin[(size_t)stream]) s = 40 + W / 2;
+    else s = W;
     return std::max<uint64_t>(1, std::min(s, smax));
 }
 
@@ -318,7 +326,7 @@ static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_
     g.C = 1;
     g.sj = nullptr;
     if (!T || !sj || sj->status != 1) return;
-    const uint64_t so = step_outputs(ps.W[r.stream], t);
+    const uint64_t so = step_outputs(ps, r.stream, t);
     if ((r.count + so - 1) / so <= T) return;
     const uint64_t P = (uint64_t)sj->D + 1;
     const uint64_t lseg = std::max<uint64_t>(64, pow2ceil(T * so));
@@ -333,7 +341,7 @@ static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_
 
 static bool wants_split(const ParamSet &ps, const Request &r, uint64_t T, const mtgp_tuning &t) {
     if (!T) return false;
-    const uint64_t so = step_outputs(ps.W[r.stream], t);
+    const uint64_t so = step_outputs(ps, r.stream, t);
     return (r.count + so - 1) / so > T && r.count > (uint64_t)ps.mexp + 128;
 }
 
@@ -547,7 +555,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
             const Seg &g = segs[i];
             const uint32_t mode = r.dtype == MTGP_F32 ? MODE_F32 : 0u;
             uint32_t *row = d_states + (size_t)r.stream * stride;
-            const uint64_t so = step_outputs(ps->W[r.stream], t);
+            const uint64_t so = step_outputs(*ps, r.stream, t);
             uint32_t *cd = (uint32_t *)(ws + L.off_cd) + i;
             auto base_item = [&](uint64_t count, uint64_t out_off) {
                 BatchItem b;
@@ -856,7 +864,7 @@ int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stri
             bt = cands[i];
         }
     }
-    const int targets[] = {0, 1024, 4096, 16384, 65536};
+    const int targets[] = {0, 1024, 2048, 4096, 8192, 16384, 65536};
     for (int T : targets) {
         if (rc) break;
         if (T == bt.jump_target_steps) continue;

@@ -22,6 +22,7 @@ struct ParamSet {
     int N = 0;                 // state words
     uint32_t mexp = 0;
     std::vector<uint32_t> W;   // step width N - pos per stream
+    std::vector<uint8_t> lin;  // 1 where rec_tbl is linear (the windowed path applies)
     uint64_t generation = 0;   // changes whenever the parameter block is rewritten
     std::mutex jump_mu;
     std::vector<std::shared_ptr<StreamJump>> jumps;  // per stream, or null
@@ -46,7 +47,7 @@ mtgp_tuning tuning_for(int N);
 int launch_tuned(int N, const mtgp_tuning &t, const LaunchArgs &a);
 
 // Outputs per step the generator achieves for step width W under a tuning.
-uint64_t step_outputs(uint32_t W, const mtgp_tuning &t);
+uint64_t step_outputs(const ParamSet &ps, int stream, const mtgp_tuning &t);
 
 // One request of a batch as the planner sees it.
 struct Request {

@@ -108,10 +108,29 @@ struct Core {
     // a single wave may also copy with overlap (the window path), which is
     // safe because its LDS reads and writes execute in instruction order and
     // the copy moves words towards lower addresses.
+    // The copy runs in chunks of up to 8 words per lane, all reads of a chunk
+    // issued before its writes; a later chunk's sources lie above every
+    // earlier chunk's destinations (h > N), so chunking keeps that order.
     static __device__ __forceinline__ void maybe_compact(uint32_t *buf, uint32_t &h,
                                                          uint32_t reach, uint32_t lane) {
         if (h + reach > (uint32_t)BUF) {
-            for (uint32_t i = lane; i < N; i += TPS) buf[i] = buf[h - N + i];
+            constexpr int R = (N + TPS - 1) / TPS;
+            constexpr int CH = R < 8 ? R : 8;
+            const uint32_t *src = buf + (h - N);
+#pragma unroll
+            for (int j0 = 0; j0 < R; j0 += CH) {
+                uint32_t tmp[CH];
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const uint32_t i = lane + (uint32_t)(j0 + j) * TPS;
+                    tmp[j] = (j0 + j < R && i < (uint32_t)N) ? src[i] : 0u;
+                }
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const uint32_t i = lane + (uint32_t)(j0 + j) * TPS;
+                    if (j0 + j < R && i < (uint32_t)N) buf[i] = tmp[j];
+                }
+            }
             group_sync<TPS>();
             h = N;
         }
