@@ -187,6 +187,10 @@ typedef struct mtgp_tuning {
     int workgroup_size;
     int jump_target_steps;  /* split streams needing more dependent steps than
                                this into jump-ahead segments; 0 = never */
+    int window_below_w;     /* with threads_per_stream = 64, streams with a
+                               linear rec_tbl and step width W = N - pos below
+                               this (at most 64) run the windowed scan instead
+                               of W-word steps; 0 = never */
 } mtgp_tuning;
 
 int mtgp_get_tuning(uint32_t mexp, mtgp_tuning *out);
@@ -196,8 +200,9 @@ int mtgp_tuning_candidates(uint32_t mexp, mtgp_tuning *out, int max_out);
 
 /* Autotuner: times every compiled launch candidate on the given batch (run
  * on a scratch copy of the states, so the caller's states are untouched),
- * then the jump-ahead target steps in {0, 1024, 2048, 4096, 8192, 16384, 65536} with the
- * fastest candidate, keeps the fastest combination as the tuning for this
+ * then the jump-ahead target steps in {0, 1024, 2048, 4096, 8192, 16384,
+ * 65536} and window_below_w in {0, 16, 24, 32, 48, 64} with the fastest
+ * candidate, keeps the fastest combination as the tuning for this
  * mexp and returns it in *best.  d_scratch holds n_streams * state_stride * 4
  * bytes (rounded up to 256) followed by the batch workspace;
  * scratch_bytes is its size.  Output buffers named by the items are

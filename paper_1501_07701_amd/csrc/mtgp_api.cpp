@@ -245,6 +245,7 @@ static mtgp_tuning default_tuning(int N) {
     t.workgroup_size = 256;
     t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 4 : 8);
     t.jump_target_steps = 2048;
+    t.window_below_w = 32;
     return t;
 }
 
@@ -260,7 +261,10 @@ static int wpb_of(const mtgp_tuning &t) {
 
 int launch_tuned(int N, const mtgp_tuning &t, const LaunchArgs &a) {
     bool found = false;
-    hipError_t e = launch_variant(N, t.threads_per_stream, t.outputs_per_lane, wpb_of(t), a, &found);
+    LaunchArgs la = a;
+    la.win_below = t.threads_per_stream == 64 ? (uint32_t)t.window_below_w : 0u;
+    hipError_t e = launch_variant(N, t.threads_per_stream, t.outputs_per_lane, wpb_of(t), la,
+                                  &found);
     if (!found)
         return fail(MTGP_EINVAL, "no kernel compiled for N=%d tps=%d k=%d wg=%d", N,
                     t.threads_per_stream, t.outputs_per_lane, t.workgroup_size);
@@ -382,6 +386,9 @@ int mtgp_set_tuning(uint32_t mexp, const mtgp_tuning *t) {
             wg == t->workgroup_size) {
             if (t->jump_target_steps < 0)
                 return fail(MTGP_EINVAL, "jump_target_steps %d < 0", t->jump_target_steps);
+            if (t->window_below_w < 0 || t->window_below_w > 64)
+                return fail(MTGP_EINVAL, "window_below_w %d outside [0, 64]",
+                            t->window_below_w);
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune[n] = *t;
             return MTGP_OK;
@@ -401,6 +408,7 @@ int mtgp_tuning_candidates(uint32_t mexp, mtgp_tuning *out, int max_out) {
         out[i].outputs_per_lane = v[i].k;
         out[i].workgroup_size = v[i].tps == 64 ? 64 * v[i].wpb : v[i].tps;
         out[i].jump_target_steps = default_tuning(n).jump_target_steps;
+        out[i].window_below_w = default_tuning(n).window_below_w;
     }
     return c;
 }

@@ -86,7 +86,9 @@ uint64_t step_outputs(const ParamSet &ps, int stream, const mtgp_tuning &t) {
     const uint64_t smax = (uint64_t)t.threads_per_stream * (uint64_t)t.outputs_per_lane;
     uint64_t s;
     if (W >= 64) s = W & ~31u;
-    else if (t.threads_per_stream == 64 && ps.lin[(size_t)stream]) s = 40 + W / 2;
+    else if (t.threads_per_stream == 64 && ps.lin[(size_t)stream] &&
+             W < (uint32_t)t.window_below_w)
+        s = 40 + W / 2;
     else s = W;
     return std::max<uint64_t>(1, std::min(s, smax));
 }
@@ -421,10 +423,11 @@ struct GraphKey {
     const void *ws;
     uint32_t nA, nB, nC;
     const void *params;
-    int N, tps, k, wg, device;
+    int N, tps, k, wg, win, device;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, device) <
-               std::tie(o.ws, o.nA, o.nB, o.nC, o.params, o.N, o.tps, o.k, o.wg, o.device);
+        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, win, device) <
+               std::tie(o.ws, o.nA, o.nB, o.nC, o.params, o.N, o.tps, o.k, o.wg, o.win,
+                        o.device);
     }
 };
 std::mutex g_graph_mu;
@@ -481,6 +484,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
     sig = mix(sig, ws_bytes);
     sig = mix(sig, ((uint64_t)t.threads_per_stream << 48) ^ ((uint64_t)t.outputs_per_lane << 32) ^
                        ((uint64_t)t.workgroup_size << 16) ^ (uint64_t)(uint32_t)t.jump_target_steps);
+    sig = mix(sig, (uint64_t)(uint32_t)t.window_below_w);
     for (const Request &r : reqs) {
         sig = mix(sig, ((uint64_t)(uint32_t)r.stream << 32) | r.dtype);
         sig = mix(sig, r.count);
@@ -651,7 +655,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
     int dev = 0;
     (void)hipGetDevice(&dev);
     GraphKey key{d_ws, nA, nB, nC, d_params, ps->N, t.threads_per_stream, t.outputs_per_lane,
-                 t.workgroup_size, dev};
+                 t.workgroup_size, t.window_below_w, dev};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -855,6 +859,7 @@ int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stri
     int rc = MTGP_OK;
     for (int i = 0; i < nc && rc == MTGP_OK; ++i) {
         cands[i].jump_target_steps = cur.jump_target_steps;
+        cands[i].window_below_w = cur.window_below_w;
         float ms = 0.f;
         rc = time_one(cands[i], &ms);
         if (rc) break;
@@ -870,6 +875,26 @@ int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stri
         if (T == bt.jump_target_steps) continue;
         mtgp_tuning t = bt;
         t.jump_target_steps = T;
+        float ms = 0.f;
+        rc = time_one(t, &ms);
+        if (rc == MTGP_OK && ms < best_ms) {
+            best_ms = ms;
+            bt = t;
+        }
+    }
+    // the window threshold matters only for one-wave tunings and streams
+    // with a linear rec_tbl and W < 64
+    bool narrow = false;
+    for (int i = 0; i < n_items && !narrow; ++i) {
+        const int k = h_items[i].stream_id;
+        narrow = k >= 0 && k < ps->n && ps->lin[(size_t)k] && ps->W[(size_t)k] < 64u;
+    }
+    const int thresholds[] = {0, 16, 24, 32, 48, 64};
+    for (int wb : thresholds) {
+        if (rc || !narrow || bt.threads_per_stream != 64) break;
+        if (wb == bt.window_below_w) continue;
+        mtgp_tuning t = bt;
+        t.window_below_w = wb;
         float ms = 0.f;
         rc = time_one(t, &ms);
         if (rc == MTGP_OK && ms < best_ms) {

@@ -30,7 +30,7 @@ enum : uint32_t {
     P_WIN_MAT = 128,     // nibble tables of M^(E*2^r): [round][nibble][16]
     P_WORDS = 1024,      // 4 KB per stream
 };
-constexpr int WIN_EMAX = 16;
+constexpr int WIN_EMAX = 8;
 constexpr int WIN_MAXROUNDS = 5;
 constexpr int WIN_MAT_WORDS = 128;   // 8 nibbles x 16 entries
 
@@ -81,6 +81,7 @@ struct LaunchArgs {
     uint32_t plain_mode;
     uint32_t *counter;
     uint32_t *err;
+    uint32_t win_below;      // window path for eligible streams with W below this
     bool persistent;
     int num_cus;
     void *stream;

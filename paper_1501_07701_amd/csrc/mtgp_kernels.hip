@@ -62,11 +62,17 @@ struct Core {
     static constexpr int BUF = buf_words(N, SMAX);
     static_assert(BUF >= 2 * N + SMAX, "compaction would overlap");
     static_assert(N > 64, "the small-step path assumes N > 64");
-    // LDS per group: the state buffer, the recursion and output tables, a
-    // 64-word exchange area and the window path's scan matrices.
-    static constexpr int SCR = BUF + 32;
-    static constexpr int MATS = SCR + 64;
-    static constexpr int LDS_WORDS = MATS + WIN_MAXROUNDS * WIN_MAT_WORDS;
+    // Window path (one wave, W < 64, linear table): a buffer of at least
+    // N + WNMAX words, then the recursion and output tables, a 64-word
+    // exchange area and the scan matrices.  The per-wave LDS block is the
+    // larger of the two layouts; the window buffer takes whatever the
+    // wide layout leaves.
+    static constexpr int WNMAX = (N - 1) < 64 * WIN_EMAX ? (N - 1) : 64 * WIN_EMAX;
+    static constexpr int WTAIL = 32 + 64 + WIN_MAXROUNDS * WIN_MAT_WORDS;
+    static constexpr int WLDS = (N + WNMAX + 63) / 64 * 64 + WTAIL;
+    static constexpr int LDS_WORDS = (BUF + 32) > WLDS ? (BUF + 32) : WLDS;
+    static constexpr int WBUF = LDS_WORDS - WTAIL;
+    static_assert(WBUF >= N + WNMAX, "window buffer too small");
 
     struct Step {  // per-item values, uniform across the group
         uint32_t pos, sh1, sh2, mask, W;
@@ -103,17 +109,19 @@ struct Core {
     }
 
     // Copies the newest N words to the front of the buffer when a step of
-    // `reach` words would run past its end.  With several waves the source
-    // [h-N, h) and destination [0, N) never overlap (h > BUF - SMAX >= 2N);
+    // `reach` words would run past its end (LIM words).  With several waves
+    // the source [h-N, h) and destination [0, N) never overlap
+    // (h > BUF - SMAX >= 2N);
     // a single wave may also copy with overlap (the window path), which is
     // safe because its LDS reads and writes execute in instruction order and
     // the copy moves words towards lower addresses.
     // The copy runs in chunks of up to 8 words per lane, all reads of a chunk
     // issued before its writes; a later chunk's sources lie above every
     // earlier chunk's destinations (h > N), so chunking keeps that order.
+    template <int LIM = BUF>
     static __device__ __forceinline__ void maybe_compact(uint32_t *buf, uint32_t &h,
                                                          uint32_t reach, uint32_t lane) {
-        if (h + reach > (uint32_t)BUF) {
+        if (h + reach > (uint32_t)LIM) {
             constexpr int R = (N + TPS - 1) / TPS;
             constexpr int CH = R < 8 ? R : 8;
             const uint32_t *src = buf + (h - N);
@@ -188,67 +196,63 @@ struct Core {
     }
 
     // Windowed steps for W < 64 with a linear recursion table, one wave.
-    // A window of Wn <= N-1 words only reads words older than its start for
+    // A window of wn <= N-1 words only reads words older than its start for
     // x_{n-N} and x_{n-N+1}, so all of them are loaded first.  What remains
     // is the tap chain x_n = G(X_n) ^ M x_{n-W} per residue class n mod W,
     // which is affine: class r is cut into q chunks of E elements (one lane
     // each); every lane runs its chunk from a zero carry, a Hillis-Steele
     // scan with M^(E*2^k) gives each lane its true carry, and the lane
     // reruns its chunk from it.  Tempering and stores then run as one
-    // coalesced pass over the window.
-    template <bool F32>
-    static __device__ __forceinline__ void steps_window(const Step &p,
-                                                        const uint32_t *__restrict__ prm,
-                                                        uint32_t *__restrict__ buf,
-                                                        const uint32_t *__restrict__ tbl,
-                                                        gptr<uint32_t> gout, gptr<uint32_t> raw,
-                                                        bool want_raw, uint64_t count,
-                                                        uint32_t &h, uint64_t &done,
-                                                        uint32_t lane) {
-        uint32_t *scr = buf + (SCR - 0);
-        uint32_t *mats = buf + MATS;
+    // coalesced pass over the window.  E is a compile-time constant so the
+    // element loops are straight-line; lanes past the window end compute
+    // junk that they write to the exchange area.
+    template <bool F32, int E>
+    static __device__ __forceinline__ void steps_window_e(const Step &p,
+                                                          const uint32_t *__restrict__ prm,
+                                                          uint32_t *__restrict__ buf,
+                                                          gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                          bool want_raw, uint64_t count,
+                                                          uint32_t &h, uint64_t &done,
+                                                          uint32_t lane) {
+        const uint32_t *tbl = buf + WBUF;
+        uint32_t *scr = buf + WBUF + 32;
+        uint32_t *mats = scr + 64;
         const uint32_t W = p.W;
-        const uint32_t wn = prm[P_WIN_WN], E = prm[P_WIN_E], q = prm[P_WIN_Q];
+        const uint32_t wn = prm[P_WIN_WN], q = prm[P_WIN_Q];
         const uint32_t rounds = prm[P_WIN_ROUNDS];
         for (uint32_t i = lane; i < rounds * WIN_MAT_WORDS; i += 64) mats[i] = prm[P_WIN_MAT + i];
         const uint32_t r = lane / q, sub = lane - (lane / q) * q;
         const bool lane_ok = r < W;
-        const uint32_t i0 = sub * E;
+        const uint32_t i0 = sub * (uint32_t)E;
+        const uint32_t off0 = r + W * i0;  // the lane's first element in the window
         group_sync<TPS>();
         while (done < count) {
             const uint64_t rem = count - done;
             const uint32_t wc = rem < wn ? (uint32_t)rem : wn;
-            maybe_compact(buf, h, wn + 64, lane);
+            maybe_compact<WBUF>(buf, h, wc, lane);
             // this lane's elements: class r, indices i0 .. i0+cnt-1
             const uint32_t lr = (lane_ok && wc > r) ? (wc - 1 - r) / W + 1 : 0u;
-            const uint32_t cnt = lr > i0 ? (lr - i0 < E ? lr - i0 : E) : 0u;
-            uint32_t X[WIN_EMAX];
+            const uint32_t cnt = lr > i0 ? (lr - i0 < (uint32_t)E ? lr - i0 : (uint32_t)E) : 0u;
+            uint32_t X[E];
 #pragma unroll
-            for (int j = 0; j < WIN_EMAX; ++j) {
-                if (j < (int)E) {
-                    const uint32_t pp = r + W * (i0 + j);
-                    const uint32_t idx = ((uint32_t)j < cnt) ? h + pp - N : h - N;
-                    const uint32_t a = buf[idx], b = buf[idx + 1];
-                    const uint32_t x0 = (a & p.mask) ^ b;
-                    X[j] = x0 ^ (x0 << p.sh1);
-                }
+            for (int j = 0; j < E; ++j) {
+                const uint32_t idx = ((uint32_t)j < cnt) ? h + off0 + W * j - N : h - N;
+                const uint32_t a = buf[idx], b = buf[idx + 1];
+                const uint32_t x0 = (a & p.mask) ^ b;
+                X[j] = x0 ^ (x0 << p.sh1);
             }
             // chunk from a zero carry (the first chunk of a class from its
             // true carry, the class's last word before the window)
             uint32_t c = (sub == 0 && lane_ok) ? buf[h + r - W] : 0u;
-            uint32_t v[WIN_EMAX];
-            uint32_t last = 0;
+            uint32_t v[E];
 #pragma unroll
-            for (int j = 0; j < WIN_EMAX; ++j) {
-                if (j < (int)E) {
-                    c = rec<true>(p, tbl, X[j] ^ (c >> p.sh2));
-                    v[j] = c;
-                    last = c;
-                }
+            for (int j = 0; j < E; ++j) {
+                c = rec<false>(p, tbl, X[j] ^ (c >> p.sh2));
+                v[j] = c;
             }
             if (rounds) {
                 // u_s <- u_s ^ M^(E*d) u_{s-d}: true last word of each chunk
-                uint32_t u = last;
+                uint32_t u = v[E - 1];
                 for (uint32_t k = 0; k < rounds; ++k) {
                     const uint32_t d = 1u << k;
                     scr[lane] = u;
@@ -264,17 +268,17 @@ struct Core {
                 if (sub > 0) {
                     c = cin;
 #pragma unroll
-                    for (int j = 0; j < WIN_EMAX; ++j) {
-                        if (j < (int)E) {
-                            c = rec<true>(p, tbl, X[j] ^ (c >> p.sh2));
-                            v[j] = c;
-                        }
+                    for (int j = 0; j < E; ++j) {
+                        c = rec<false>(p, tbl, X[j] ^ (c >> p.sh2));
+                        v[j] = c;
                     }
                 }
             }
 #pragma unroll
-            for (int j = 0; j < WIN_EMAX; ++j)
-                if (j < (int)E && (uint32_t)j < cnt) buf[h + r + W * (i0 + j)] = v[j];
+            for (int j = 0; j < E; ++j) {
+                const uint32_t dst = ((uint32_t)j < cnt) ? h + off0 + W * j : WBUF + 32 + lane;
+                buf[dst] = v[j];
+            }
             group_sync<TPS>();
             // tempering and stores, coalesced over the window
             for (uint32_t pp = lane; pp < wc; pp += 64) {
@@ -286,6 +290,24 @@ struct Core {
             group_sync<TPS>();
             h += wc;
             done += wc;
+        }
+    }
+
+    template <bool F32>
+    static __device__ __forceinline__ void steps_window(const Step &p,
+                                                        const uint32_t *__restrict__ prm,
+                                                        uint32_t *__restrict__ buf,
+                                                        gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                        bool want_raw, uint64_t count,
+                                                        uint32_t &h, uint64_t &done,
+                                                        uint32_t lane) {
+        switch (prm[P_WIN_E]) {
+#define MTGP_WE(E) \
+    case E: steps_window_e<F32, E>(p, prm, buf, gout, raw, want_raw, count, h, done, lane); break;
+            MTGP_WE(1) MTGP_WE(2) MTGP_WE(3) MTGP_WE(4)
+            MTGP_WE(5) MTGP_WE(6) MTGP_WE(7) MTGP_WE(8)
+#undef MTGP_WE
+            default: break;
         }
     }
 
@@ -365,8 +387,10 @@ struct Core {
     static __device__ __forceinline__ void run(const uint32_t *__restrict__ prm,
                                                const BatchItem &item,
                                                uint32_t *__restrict__ buf, uint32_t lane,
-                                               uint32_t *__restrict__ err) {
-        uint32_t *__restrict__ tbl = buf + BUF;
+                                               uint32_t *__restrict__ err, uint32_t win_below) {
+        // a stream takes the window path when the host gave it window data
+        const bool win = TPS == 64 && prm[P_WIN_E] != 0u && prm[P_W] < win_below;
+        uint32_t *__restrict__ tbl = buf + (win ? WBUF : BUF);
         Step p;
         p.pos = prm[P_POS];
         p.sh1 = prm[P_SH1];
@@ -399,9 +423,11 @@ struct Core {
 
         uint32_t h = N;  // buffer index of the next new word
         uint64_t done = 0;
-        if (TPS == 64 && p.W < 64) {
+        if (win) {
+            steps_window<F32>(p, prm, buf, gout, raw, want_raw, count, h, done, lane);
+        } else if (TPS == 64 && p.W < 64) {
             if (lin)
-                steps_window<F32>(p, prm, buf, tbl, gout, raw, want_raw, count, h, done, lane);
+                steps_small<F32, true>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
             else
                 steps_small<F32, false>(p, buf, tbl, gout, raw, want_raw, count, h, done, lane);
         } else {
@@ -434,7 +460,7 @@ template <int N, int TPS, int K, int WPB>
 __global__ void __launch_bounds__(TPS == 64 ? 64 * WPB : TPS)
 gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
            uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
-           uint32_t persistent, PlainArgs plain) {
+           uint32_t persistent, uint32_t win_below, PlainArgs plain) {
     using C = Core<N, TPS, K>;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_claim;
@@ -474,9 +500,9 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
         const uint32_t *prm = params + (uint64_t)item.stream * P_WORDS;
         if (item.count > 0) {
             if (item.mode & MODE_F32)
-                C::template run<true>(prm, item, buf, lane, err);
+                C::template run<true>(prm, item, buf, lane, err, win_below);
             else
-                C::template run<false>(prm, item, buf, lane, err);
+                C::template run<false>(prm, item, buf, lane, err, win_below);
         }
         if (item.flag != 0) {
             // Publish completion of the request to the host once its last
@@ -633,7 +659,8 @@ static hipError_t launch_gen(const LaunchArgs &a) {
     PlainArgs plain{a.plain_states, a.plain_stride, a.plain_mode, a.plain_out, a.plain_count};
     (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(fn, dim3(grid), dim3(threads), lds, (hipStream_t)a.stream, a.params,
-                       a.items, a.n_items, a.counter, a.err, a.persistent ? 1u : 0u, plain);
+                       a.items, a.n_items, a.counter, a.err, a.persistent ? 1u : 0u,
+                       a.win_below, plain);
     return hipGetLastError();
 }
 

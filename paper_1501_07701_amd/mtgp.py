@@ -41,14 +41,15 @@ class Work(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("threads_per_stream", ctypes.c_int), ("outputs_per_lane", ctypes.c_int),
-                ("workgroup_size", ctypes.c_int), ("jump_target_steps", ctypes.c_int)]
+                ("workgroup_size", ctypes.c_int), ("jump_target_steps", ctypes.c_int),
+                ("window_below_w", ctypes.c_int)]
 
     def as_tuple(self):
         return (self.threads_per_stream, self.outputs_per_lane, self.workgroup_size,
-                self.jump_target_steps)
+                self.jump_target_steps, self.window_below_w)
 
     def __repr__(self):
-        return "Tuning(tps=%d, k=%d, wg=%d, jump=%d)" % self.as_tuple()
+        return "Tuning(tps=%d, k=%d, wg=%d, jump=%d, window_below=%d)" % self.as_tuple()
 
 
 class ServerOpts(ctypes.Structure):
@@ -254,10 +255,16 @@ def get_tuning(mexp: int) -> Tuning:
     return t
 
 
-def set_tuning(mexp: int, tps: int, k: int, wg: int, jump_target_steps=None) -> None:
+def set_tuning(mexp: int, tps: int, k: int, wg: int, jump_target_steps=None,
+               window_below_w=None) -> None:
+    """Sets the launch tuning of an exponent; the jump target and the window
+    threshold keep their current values unless given."""
+    cur = get_tuning(mexp)
     if jump_target_steps is None:
-        jump_target_steps = get_tuning(mexp).jump_target_steps
-    t = Tuning(tps, k, wg, jump_target_steps)
+        jump_target_steps = cur.jump_target_steps
+    if window_below_w is None:
+        window_below_w = cur.window_below_w
+    t = Tuning(tps, k, wg, jump_target_steps, window_below_w)
     _check(lib().mtgp_set_tuning(mexp, ctypes.byref(t)), "mtgp_set_tuning")
 
 

@@ -121,6 +121,10 @@ def test_tuning_tables(lib):
         mtgp.set_tuning(mexp, *t0.as_tuple())
     with pytest.raises(mtgp.MTGPError):
         mtgp.set_tuning(11213, 64, 3, 256)
+    for bad in (-1, 65):
+        with pytest.raises(mtgp.MTGPError) as e:
+            mtgp.set_tuning(11213, 64, 4, 256, 2048, bad)
+        assert "window_below_w" in str(e.value)
 
 
 def test_strerror(lib):

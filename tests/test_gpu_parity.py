@@ -114,26 +114,34 @@ def test_nonlinear_recursion_tables(torch, mexp):
     g.close()
 
 
-@pytest.mark.parametrize("w", [2, 3, 5, 16, 21, 31, 32, 33, 63])
+@pytest.mark.parametrize("w", [2, 3, 5, 16, 21, 23, 31, 32, 33, 63])
 def test_every_short_step_width(torch, w):
-    """The windowed path for each lanes-per-class split (q = 64 // W)."""
-    _say("case short W=%d" % w)
+    """Each lanes-per-class split (q = 64 // W) of the windowed path, and the
+    W-word step path for the same streams (window threshold 0)."""
     for mexp in (11213, 44497):
+        t0 = mtgp.get_tuning(mexp)
         N = mexp // 32 + 1
         p = workloads.make_params(mexp, 3, 0x5757 + w)
         p[:, 1] = N - w
         p[1, 3] = 0                                      # sh2 = 0
         p[2, 2], p[2, 3] = 31, 31
         seeds = np.array([0, 7, 0xFFFFFFFF], dtype=np.uint32)
-        g = mtgp.Generators(p, seeds)
         calls = [1, w - 1 if w > 1 else 1, 5 * N + 3, 2 * N]
-        got = [_host(g.generate(c, mtgp.U32)).reshape(3, c) for c in calls]
         exp, exp_states = _oracle_run(p, seeds, calls, [False] * len(calls))
-        for k in range(3):
-            for i in range(len(calls)):
-                assert np.array_equal(got[i][k], exp[k][i]), (mexp, k, i)
-        assert np.array_equal(g.states_host(), exp_states)
-        g.close()
+        try:
+            for below in (64, 0):
+                _say("case short W=%d mexp=%d window_below=%d" % (w, mexp, below))
+                tt = t0.as_tuple()
+                mtgp.set_tuning(mexp, tt[0], tt[1], tt[2], tt[3], below)
+                g = mtgp.Generators(p, seeds)
+                got = [_host(g.generate(c, mtgp.U32)).reshape(3, c) for c in calls]
+                for k in range(3):
+                    for i in range(len(calls)):
+                        assert np.array_equal(got[i][k], exp[k][i]), (mexp, below, k, i)
+                assert np.array_equal(g.states_host(), exp_states)
+                g.close()
+        finally:
+            mtgp.set_tuning(mexp, *t0.as_tuple())
 
 
 @pytest.mark.parametrize("mexp", [11213, 44497])
