@@ -157,7 +157,7 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
         (e = d_out.alloc((size_t)cn * (R - N) * 4)) != hipSuccess ||
         (e = d_items.alloc((size_t)cn * sizeof(BatchItem))) != hipSuccess ||
         (e = d_counter.alloc(256)) != hipSuccess ||
-        (e = d_jitems.alloc((size_t)cn * sizeof(JumpItem))) != hipSuccess ||
+        (e = d_jitems.alloc((size_t)cn * JUMP_BLOCK * sizeof(JumpItem))) != hipSuccess ||
         (e = d_poly.alloc((size_t)cn * PW * 4)) != hipSuccess ||
         (e = d_vout.alloc((size_t)cn * V * 4)) != hipSuccess)
         return hip_fail(e, "hipMalloc(jump planning)");
@@ -209,7 +209,9 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
                 P[j] = annihilator(&raw[(size_t)j * R], R, pass == 0 ? quick : all);
             });
             // device check: y_t = sum_i p_i x_{t+i} must vanish for t = 1..D
-            std::vector<JumpItem> jit((size_t)m);
+            // one item per block: each stream's check runs on its own
+            std::vector<JumpItem> jit((size_t)m * JUMP_BLOCK);
+            std::memset(jit.data(), 0, jit.size() * sizeof(JumpItem));
             std::vector<uint32_t> pw((size_t)m * PW, 0u);
             int nj = 0;
             std::vector<int> which;
@@ -219,7 +221,7 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
                 if (D < 1 || D > mexp) continue;
                 const std::vector<uint32_t> w = pack32(P[j], D + 1);
                 std::memcpy(&pw[(size_t)nj * PW], w.data(), w.size() * 4);
-                JumpItem &ji = jit[nj];
+                JumpItem &ji = jit[(size_t)nj * JUMP_BLOCK];
                 ji.raw = (uint64_t)(uintptr_t)((uint32_t *)d_raw.p + (size_t)j * R);
                 ji.poly = (uint64_t)(uintptr_t)((uint32_t *)d_poly.p + (size_t)nj * PW);
                 ji.out = (uint64_t)(uintptr_t)((uint32_t *)d_vout.p + (size_t)nj * V);
@@ -231,10 +233,12 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
             if (nj == 0) break;
             if ((e = hipMemcpyAsync(d_poly.p, pw.data(), (size_t)nj * PW * 4,
                                     hipMemcpyHostToDevice, s)) != hipSuccess ||
-                (e = hipMemcpyAsync(d_jitems.p, jit.data(), (size_t)nj * sizeof(JumpItem),
+                (e = hipMemcpyAsync(d_jitems.p, jit.data(),
+                                    (size_t)nj * JUMP_BLOCK * sizeof(JumpItem),
                                     hipMemcpyHostToDevice, s)) != hipSuccess)
                 return hip_fail(e, "hipMemcpyAsync(check items)");
-            if ((e = launch_jump((const JumpItem *)d_jitems.p, (uint32_t)nj, device_cus(), s)) !=
+            if ((e = launch_jump((const JumpItem *)d_jitems.p, (uint32_t)nj * JUMP_BLOCK,
+                                 device_cus(), s)) !=
                 hipSuccess)
                 return hip_fail(e, "jump kernel (check)");
             if ((e = hipMemcpyAsync(vout.data(), d_vout.p, (size_t)nj * V * 4,
@@ -355,7 +359,7 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_
             continue;
         }
         ++nA;
-        nB += (size_t)g.C - 1;
+        nB += ((size_t)g.C - 1 + JUMP_BLOCK - 1) / JUMP_BLOCK * JUMP_BLOCK;
         nC += (size_t)g.C;
         poly_words += ((size_t)g.C - 1) * (((size_t)g.sj->D + 31) / 32);
         raw_words += ((size_t)ps.N + (size_t)g.sj->D + 1 + 63) / 64 * 64;
@@ -607,6 +611,11 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
                 std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
                 poly_off += pw * 4;
                 B.push_back(j);
+            }
+            while (B.size() % JUMP_BLOCK) {  // pad this stream's block
+                JumpItem z;
+                std::memset(&z, 0, sizeof z);
+                B.push_back(z);
             }
             // C: segments
             for (int k = 0; k < g.C; ++k) {

@@ -61,10 +61,14 @@ static_assert(sizeof(BatchItem) == 80, "BatchItem layout");
 
 // Jump evaluation item (32 bytes): out[m] = XOR_{i < nbits, g_i = 1}
 // raw[1 + i + m] for m < m_count.
+// Jump items are launched in blocks of JUMP_BLOCK: the items of a block
+// share raw, nbits and m (one stream); null items (out == 0) pad a block and
+// the first item of a block is never null.
+constexpr int JUMP_BLOCK = 4;
 struct JumpItem {
-    uint64_t raw;     // words x_0, x_1, ... of a stream
+    uint64_t raw;     // words x_0, x_1, ... of a stream (at least nbits + m + 1)
     uint64_t poly;    // coefficients g_0 .. g_{nbits-1}, 32 per uint32 word
-    uint64_t out;     // m words
+    uint64_t out;     // m words; 0 = padding
     uint32_t nbits;
     uint32_t m;
 };

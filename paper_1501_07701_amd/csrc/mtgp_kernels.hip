@@ -525,68 +525,100 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
     }
 }
 
-// Jump evaluation: out[m] = XOR over the set bits i < D of g of raw[1+i+m],
-// for m < M.  One wave per item (JUMP_WAVES items per workgroup); the words
-// are staged through the wave's LDS region in chunks of JUMP_CH coefficients
-// plus the output tail, and lane l owns output words m0 + l + 64 j of the
-// current pass.
-constexpr int JUMP_WAVES = 4;
-constexpr int JUMP_CH = 2048;   // coefficients per LDS chunk
+// Jump evaluation: out[m] = XOR over the set bits i < D of g of r[i+m] with
+// r[n] = raw[1+n], for m < M.  Items come in blocks of JUMP_WAVES: one
+// workgroup per block, one wave per item; the items of a block use the same
+// words r (same stream, D and M) and null items (out == 0) only pad a block.
+// Coefficients are taken four at a time: for a nibble value v of g at
+// coefficients 4c..4c+3 the wave adds Q_v[4c+m], where
+// Q_v[n] = XOR over the set bits j of v of r[n+j].  The workgroup builds the
+// 15 planes Q_1..Q_15 for a chunk of JUMP_CH coefficients and JUMP_MT outputs
+// in LDS once, and every wave of the block reads them: per output word one
+// LDS read per nonzero nibble instead of one per set bit.
+constexpr int JUMP_WAVES = JUMP_BLOCK;
+constexpr int JUMP_CH = 512;    // coefficients per chunk (multiple of 32)
 constexpr int JUMP_JA = 8;      // output words per lane per pass
 constexpr int JUMP_MT = 64 * JUMP_JA;
+constexpr int JUMP_PL = JUMP_CH + JUMP_MT;  // plane length (words)
+constexpr int JUMP_LDS_BYTES = 15 * JUMP_PL * 4;
 
 template <int JA>
-__device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ raw,
+__device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ r,
                                           const uint32_t *__restrict__ g,
-                                          uint32_t *__restrict__ out, uint32_t D, uint32_t m0,
-                                          uint32_t mt, uint32_t *__restrict__ base,
-                                          uint32_t lane) {
+                                          uint32_t *__restrict__ out, bool active, uint32_t D,
+                                          uint32_t rlen, uint32_t m0, uint32_t mt,
+                                          uint32_t *__restrict__ planes, uint32_t lane) {
     uint32_t acc[JA];
 #pragma unroll
     for (int j = 0; j < JA; ++j) acc[j] = 0;
     for (uint32_t i0 = 0; i0 < D; i0 += JUMP_CH) {
         const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
-        group_sync<64>();
-        for (uint32_t j = lane; j < ch + mt; j += 64) base[j] = raw[i0 + m0 + j];
-        group_sync<64>();
-        const uint32_t nw = (ch + 31) / 32;
-        for (uint32_t w = 0; w < nw; ++w) {
-            uint32_t bits = g[(i0 >> 5) + w];
-            if (w == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
-            while (bits) {
-                const uint32_t i = 32 * w + (uint32_t)__builtin_ctz(bits);
-                bits &= bits - 1u;
-                const uint32_t *src = base + i + lane;
+        const uint32_t L = ch + mt;
+        const uint32_t base = i0 + m0;
+        __syncthreads();  // every wave is done with the previous chunk's planes
+        for (uint32_t t = threadIdx.x; t < L; t += 64 * JUMP_WAVES) {
+            const uint32_t n = base + t;
+            uint32_t w[4];
 #pragma unroll
-                for (int j = 0; j < JA; ++j) acc[j] ^= src[64 * j];
+            for (int j = 0; j < 4; ++j) w[j] = (n + j < rlen) ? r[n + j] : 0u;
+            uint32_t q[16];
+            q[0] = 0;
+#pragma unroll
+            for (int v = 1; v < 16; ++v) {
+                const int low = v & -v;
+                const int bit = low == 1 ? 0 : (low == 2 ? 1 : (low == 4 ? 2 : 3));
+                q[v] = q[v & (v - 1)] ^ w[bit];
+                planes[(v - 1) * JUMP_PL + t] = q[v];
+            }
+        }
+        __syncthreads();
+        if (active) {
+            const uint32_t nw = (ch + 31) / 32;
+            for (uint32_t cw = 0; cw < nw; ++cw) {
+                uint32_t bits = __builtin_amdgcn_readfirstlane(g[(i0 >> 5) + cw]);
+                if (cw == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const uint32_t v = (bits >> (4 * k)) & 15u;
+                    if (v == 0) continue;
+                    const uint32_t *src = planes + (v - 1) * JUMP_PL + 32 * cw + 4 * k + lane;
+#pragma unroll
+                    for (int j = 0; j < JA; ++j) acc[j] ^= src[64 * j];
+                }
             }
         }
     }
+    if (active) {
 #pragma unroll
-    for (int j = 0; j < JA; ++j) {
-        const uint32_t m = lane + 64 * j;
-        if (m < mt) out[m0 + m] = acc[j];
+        for (int j = 0; j < JA; ++j) {
+            const uint32_t m = lane + 64 * j;
+            if (m < mt) out[m0 + m] = acc[j];
+        }
     }
 }
 
 __global__ void __launch_bounds__(64 * JUMP_WAVES)
 jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
-    __shared__ uint32_t lds[JUMP_WAVES][JUMP_CH + JUMP_MT];
+    extern __shared__ uint32_t planes[];
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t *base = lds[wave];
-    for (uint32_t it = blockIdx.x * JUMP_WAVES + wave; it < n_items;
-         it += gridDim.x * JUMP_WAVES) {
-        const JumpItem jit = items[it];
-        const uint32_t *raw = reinterpret_cast<const uint32_t *>(jit.raw) + 1;
+    const uint32_t n_blocks = (n_items + JUMP_WAVES - 1) / JUMP_WAVES;
+    for (uint32_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
+        const JumpItem lead = items[blk * JUMP_WAVES];
+        const uint32_t mine = blk * JUMP_WAVES + wave;
+        JumpItem jit = lead;
+        jit.out = 0;
+        if (mine < n_items) jit = items[mine];
+        const bool active = jit.out != 0;
+        const uint32_t *r = reinterpret_cast<const uint32_t *>(lead.raw) + 1;
         const uint32_t *g = reinterpret_cast<const uint32_t *>(jit.poly);
         uint32_t *out = reinterpret_cast<uint32_t *>(jit.out);
-        const uint32_t D = jit.nbits, M = jit.m;
+        const uint32_t D = lead.nbits, M = lead.m, rlen = lead.nbits + lead.m;
         for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
             const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
             switch ((mt + 63) / 64) {
 #define MTGP_JP(JA) \
-    case JA: jump_pass<JA>(raw, g, out, D, m0, mt, base, lane); break;
+    case JA: jump_pass<JA>(r, g, out, active, D, rlen, m0, mt, planes, lane); break;
                 MTGP_JP(1) MTGP_JP(2) MTGP_JP(3) MTGP_JP(4)
                 MTGP_JP(5) MTGP_JP(6) MTGP_JP(7) MTGP_JP(8)
 #undef MTGP_JP
@@ -719,11 +751,20 @@ hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs
 
 hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s) {
     if (n_items == 0) return hipSuccess;
+    static bool attr_set = false;  // benign race: idempotent attribute
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)jump_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           JUMP_LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
     int grid = (int)((n_items + JUMP_WAVES - 1) / JUMP_WAVES);
-    const int cap = num_cus * 4;  // 4 blocks of 40 KB LDS fill a CU
+    const int cap = num_cus * 2;  // two blocks of 60 KB planes fit a CU's LDS
     if (grid > cap) grid = cap;
     (void)hipGetLastError();  // report this launch only
-    hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(64 * JUMP_WAVES), 0, s, items, n_items);
+    hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(64 * JUMP_WAVES), JUMP_LDS_BYTES, s, items,
+                       n_items);
     return hipGetLastError();
 }
 
