@@ -237,15 +237,16 @@ static std::mutex g_tune_mu;
 static std::map<int, mtgp_tuning> g_tune;  // keyed by N
 
 static mtgp_tuning default_tuning(int N) {
-    // One wave per stream, 4 waves per workgroup; K sized so a step can
-    // cover the typical step width W (uniform in [2, N-1]); streams needing
-    // more than 2048 dependent steps are split by jump-ahead.
+    // One wave per stream, 4 waves per workgroup; K trades step width
+    // against LDS per wave (occupancy); streams needing more than 4096
+    // dependent steps are split by jump-ahead; narrow streams below W = 56
+    // take the windowed scan (it is ahead of W-word steps up to about there).
     mtgp_tuning t;
     t.threads_per_stream = 64;
     t.workgroup_size = 256;
-    t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 4 : 8);
-    t.jump_target_steps = 2048;
-    t.window_below_w = 32;
+    t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 2 : 8);
+    t.jump_target_steps = 4096;
+    t.window_below_w = 56;
     return t;
 }
 

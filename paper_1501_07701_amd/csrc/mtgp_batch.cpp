@@ -79,8 +79,8 @@ static uint64_t pow2ceil(uint64_t v) {
 
 // Cost model: outputs a stream yields per dependent step of the wide path
 // (one LDS round trip).  Narrow streams with a linear rec_tbl run the
-// windowed scan instead, which measures at about 40 + W/2 outputs per
-// wide-step time whatever W is.
+// windowed scan instead, which measures at about 60 + W outputs per
+// wide-step time.
 uint64_t step_outputs(const ParamSet &ps, int stream, const mtgp_tuning &t) {
     const uint32_t W = ps.W[(size_t)stream];
     const uint64_t smax = (uint64_t)t.threads_per_stream * (uint64_t)t.outputs_per_lane;
@@ -88,7 +88,7 @@ uint64_t step_outputs(const ParamSet &ps, int stream, const mtgp_tuning &t) {
     if (W >= 64) s = W & ~31u;
     else if (t.threads_per_stream == 64 && ps.lin[(size_t)stream] &&
              W < (uint32_t)t.window_below_w)
-        s = 40 + W / 2;
+        s = 60 + W;
     else s = W;
     return std::max<uint64_t>(1, std::min(s, smax));
 }
