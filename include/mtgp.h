@@ -151,8 +151,8 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items,
  * call.
  *
  * Jump-ahead (not in the paper; the generator's GF(2)-linearity makes it
- * exact): a stream whose request needs more than the tuning's
- * jump_target_steps dependent steps is cut into segments that run in
+ * exact): a stream whose request needs more dependent steps than the
+ * batch's target (see mtgp_tuning) is cut into segments that run in
  * parallel.  Their start states are XOR-combinations of the stream's first
  * words given by x^(J-1) mod p, p an annihilating polynomial of the
  * stream's word sequence found by Berlekamp-Massey and checked on the device
@@ -185,8 +185,11 @@ typedef struct mtgp_tuning {
     int threads_per_stream;
     int outputs_per_lane;
     int workgroup_size;
-    int jump_target_steps;  /* split streams needing more dependent steps than
-                               this into jump-ahead segments; 0 = never */
+    int jump_target_steps;  /* 0 = never split streams by jump-ahead; else the
+                               least number of dependent steps per segment:
+                               a batch splits the streams that need more
+                               steps than max(this, its total steps over
+                               0.8 x the streams the device runs at once) */
     int window_below_w;     /* with threads_per_stream = 64, streams with a
                                linear rec_tbl and step width W = N - pos below
                                this (at most 64) run the windowed scan instead

@@ -238,14 +238,15 @@ static std::map<int, mtgp_tuning> g_tune;  // keyed by N
 
 static mtgp_tuning default_tuning(int N) {
     // One wave per stream, 4 waves per workgroup; K trades step width
-    // against LDS per wave (occupancy); streams needing more than 4096
-    // dependent steps are split by jump-ahead; narrow streams below W = 56
-    // take the windowed scan (it is ahead of W-word steps up to about there).
+    // against LDS per wave (occupancy); jump-ahead splits streams on a
+    // batch's critical path, with segments of at least 1024 dependent steps;
+    // narrow streams below W = 56 take the windowed scan (it is ahead of
+    // W-word steps up to about there).
     mtgp_tuning t;
     t.threads_per_stream = 64;
     t.workgroup_size = 256;
     t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 2 : 8);
-    t.jump_target_steps = 4096;
+    t.jump_target_steps = 1024;
     t.window_below_w = 56;
     return t;
 }

@@ -71,12 +71,6 @@ static void parallel_for(int n, F f) {
     for (auto &x : th) x.join();
 }
 
-static uint64_t pow2ceil(uint64_t v) {
-    uint64_t p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
 // Cost model: outputs a stream yields per dependent step of the wide path
 // (one LDS round trip).  Narrow streams with a linear rec_tbl run the
 // windowed scan instead, which measures at about 60 + W outputs per
@@ -325,6 +319,27 @@ size_t batch_min_ws_bytes(int n_items) {
            al256((size_t)std::max(n_items, 0) * 4);
 }
 
+// The dependent-step target of a batch: the tuning's jump_target_steps is
+// a floor (0 disables splitting); above it the target follows the batch's
+// balanced makespan, total steps over the streams the device runs at once,
+// so that only streams on the critical path are cut and each segment is
+// short against the whole launch.
+static uint64_t effective_target(const ParamSet &ps, const std::vector<Request> &reqs,
+                                 const mtgp_tuning &t) {
+    if (t.jump_target_steps <= 0) return 0;
+    uint64_t total = 0;
+    for (const Request &r : reqs) {
+        const uint64_t so = step_outputs(ps, r.stream, t);
+        total += (r.count + so - 1) / so;
+    }
+    const int wpb = t.threads_per_stream == 64 ? t.workgroup_size / 64 : 1;
+    const int per_cu = variant_slots_per_cu(ps.N, t.threads_per_stream, t.outputs_per_lane, wpb);
+    const uint64_t slots = (uint64_t)std::max(1, per_cu) * (uint64_t)std::max(1, device_cus());
+    // about 0.8 of the resident streams' worth of steps per segment
+    const uint64_t adaptive = total * 5 / (slots * 4);
+    return std::max<uint64_t>((uint64_t)t.jump_target_steps, adaptive);
+}
+
 // Splits a request when it needs more than T dependent steps and the
 // stream's jump data is usable.
 static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_t T,
@@ -335,7 +350,8 @@ static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_
     const uint64_t so = step_outputs(ps, r.stream, t);
     if ((r.count + so - 1) / so <= T) return;
     const uint64_t P = (uint64_t)sj->D + 1;
-    const uint64_t lseg = std::max<uint64_t>(64, pow2ceil(T * so));
+    // whole 256-word blocks keep every segment's stores line-aligned
+    const uint64_t lseg = std::max<uint64_t>(256, T * so / 256 * 256);
     const uint64_t c0 = (P + 1 + lseg - 1) / lseg;   // segment 0 keeps >= 1 output past P
     const uint64_t cend = (r.count + lseg - 1) / lseg;
     if (cend <= c0) return;
@@ -514,7 +530,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         // which requests want splitting at the tuning's target
         const int N = ps->N;
         std::vector<int> want;
-        uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
+        uint64_t T = effective_target(*ps, reqs, t);
         for (size_t i = 0; i < reqs.size(); ++i) {
             segs[i].req = (int)i;
             if (wants_split(*ps, reqs[i], T, t)) want.push_back(reqs[i].stream);
@@ -770,9 +786,9 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items, i
     int rc = validate_requests(*ps, h_items, n_items);
     if (rc) return rc;
     const mtgp_tuning t = tuning_for(ps->N);
-    const uint64_t T = (uint64_t)std::max(0, t.jump_target_steps);
     std::vector<int> want;
     std::vector<Request> reqs = to_requests(h_items, n_items);
+    const uint64_t T = effective_target(*ps, reqs, t);
     for (const Request &r : reqs)
         if (wants_split(*ps, r, T, t)) want.push_back(r.stream);
     if (!want.empty()) {

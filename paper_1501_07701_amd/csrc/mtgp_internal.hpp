@@ -100,6 +100,7 @@ int variant_count(int n_words, VariantInfo *out, int max_out);
 hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs &a,
                           bool *found);
 hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s);
+int variant_slots_per_cu(int n_words, int tps, int k, int wpb);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s);
 hipError_t launch_reset(uint32_t *counter, hipStream_t s);

@@ -51,16 +51,19 @@ __device__ __forceinline__ void group_sync() {
 }
 
 // LDS buffer length (words) for a stream of N words and up to SMAX outputs
-// per step: at least 2N + SMAX so the compaction copy never overlaps itself.
-__host__ __device__ constexpr int buf_words(int N, int SMAX) {
-    return ((2 * N + 4 * SMAX) + 63) / 64 * 64;
+// per step, with room for about four steps between compactions.  Several
+// waves need at least 2N + SMAX so the compaction copy never overlaps
+// itself; a single wave copies overlapping ranges safely and needs only
+// N + SMAX.
+__host__ __device__ constexpr int buf_words(int N, int SMAX, int TPS) {
+    return ((TPS == 64 ? N : 2 * N) + 4 * SMAX + 63) / 64 * 64;
 }
 
 template <int N, int TPS, int K>
 struct Core {
     static constexpr int SMAX = TPS * K;
-    static constexpr int BUF = buf_words(N, SMAX);
-    static_assert(BUF >= 2 * N + SMAX, "compaction would overlap");
+    static constexpr int BUF = buf_words(N, SMAX, TPS);
+    static_assert(BUF >= (TPS == 64 ? N : 2 * N) + SMAX, "compaction would overlap");
     static_assert(N > 64, "the small-step path assumes N > 64");
     // Window path (one wave, W < 64, linear table): a buffer of at least
     // N + WNMAX words, then the recursion and output tables, a 64-word
@@ -111,8 +114,7 @@ struct Core {
     // Copies the newest N words to the front of the buffer when a step of
     // `reach` words would run past its end (LIM words).  With several waves
     // the source [h-N, h) and destination [0, N) never overlap
-    // (h > BUF - SMAX >= 2N);
-    // a single wave may also copy with overlap (the window path), which is
+    // (h > BUF - SMAX >= 2N); a single wave may copy with overlap, which is
     // safe because its LDS reads and writes execute in instruction order and
     // the copy moves words towards lower addresses.
     // The copy runs in chunks of up to 8 words per lane, all reads of a chunk
@@ -701,13 +703,32 @@ static size_t lds_bytes_of() {
     return (size_t)Core<N, TPS, K>::LDS_WORDS * 4 * (TPS == 64 ? WPB : 1);
 }
 
+// Streams a CU runs at once with this variant (waves for TPS = 64, else
+// workgroups), from the occupancy the runtime reports; 0 on error.
+template <int N, int TPS, int K, int WPB>
+static int slots_of() {
+    static int cached = -1;  // benign race: idempotent query
+    if (cached < 0) {
+        int per_cu = 0;
+        const int threads = TPS == 64 ? 64 * WPB : TPS;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gen_kernel<N, TPS, K, WPB>,
+                                                         threads, lds_bytes_of<N, TPS, K, WPB>()) !=
+            hipSuccess)
+            return 0;
+        cached = per_cu * (TPS == 64 ? WPB : 1);
+    }
+    return cached;
+}
+
 struct Variant {
     int N, tps, k, wpb;
     hipError_t (*launch)(const LaunchArgs &);
     size_t (*lds)();
+    int (*slots)();
 };
 
-#define MTGP_V(N, T, K, P) {N, T, K, P, &launch_gen<N, T, K, P>, &lds_bytes_of<N, T, K, P>}
+#define MTGP_V(N, T, K, P) \
+    {N, T, K, P, &launch_gen<N, T, K, P>, &lds_bytes_of<N, T, K, P>, &slots_of<N, T, K, P>}
 #define MTGP_VARIANTS(N)                                                              \
     MTGP_V(N, 64, 1, 4), MTGP_V(N, 64, 2, 4), MTGP_V(N, 64, 4, 4), MTGP_V(N, 64, 8, 4), \
     MTGP_V(N, 64, 2, 8), MTGP_V(N, 64, 4, 8), MTGP_V(N, 64, 4, 16),                   \
@@ -747,6 +768,14 @@ hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs
     }
     *found = false;
     return hipSuccess;
+}
+
+int variant_slots_per_cu(int n_words, int tps, int k, int wpb) {
+    for (const Variant &v : kVariants)
+        if (v.N == n_words && v.tps == tps && v.k == k && v.wpb == wpb &&
+            v.lds() + 64 <= kLdsBytes)
+            return v.slots();
+    return 0;
 }
 
 hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s) {
