@@ -245,7 +245,7 @@ static mtgp_tuning default_tuning(int N) {
     mtgp_tuning t;
     t.threads_per_stream = 64;
     t.workgroup_size = 256;
-    t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 2 : 8);
+    t.outputs_per_lane = N <= 128 ? 1 : (N <= 400 ? 4 : 8);
     t.jump_target_steps = 1024;
     t.window_below_w = 56;
     return t;

@@ -536,17 +536,17 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
 // Q_v[n] = XOR over the set bits j of v of r[n+j].  The workgroup builds the
 // 15 planes Q_1..Q_15 for a chunk of JUMP_CH coefficients and JUMP_MT outputs
 // in LDS once, and every wave of the block reads them: per output word one
-// LDS read per nonzero nibble instead of one per set bit.
+// LDS read per nibble instead of one per set bit.  Plane 0 stays zero, so
+// the lookups are branch-free and several nibbles' reads are in flight.
 constexpr int JUMP_WAVES = JUMP_BLOCK;
 constexpr int JUMP_CH = 512;    // coefficients per chunk (multiple of 32)
 constexpr int JUMP_JA = 8;      // output words per lane per pass
 constexpr int JUMP_MT = 64 * JUMP_JA;
 constexpr int JUMP_PL = JUMP_CH + JUMP_MT;  // plane length (words)
-constexpr int JUMP_LDS_BYTES = 15 * JUMP_PL * 4;
+constexpr int JUMP_LDS_BYTES = 16 * JUMP_PL * 4;
 
 template <int JA>
-__device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ r,
-                                          const uint32_t *__restrict__ g,
+__device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uint32_t> g,
                                           uint32_t *__restrict__ out, bool active, uint32_t D,
                                           uint32_t rlen, uint32_t m0, uint32_t mt,
                                           uint32_t *__restrict__ planes, uint32_t lane) {
@@ -557,6 +557,9 @@ __device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ r,
         const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
         const uint32_t L = ch + mt;
         const uint32_t base = i0 + m0;
+        const uint32_t nw = (ch + 31) / 32;
+        // this chunk's coefficient words, one per lane, fetched early
+        const uint32_t gv = (active && lane < nw) ? g[(i0 >> 5) + lane] : 0u;
         __syncthreads();  // every wave is done with the previous chunk's planes
         for (uint32_t t = threadIdx.x; t < L; t += 64 * JUMP_WAVES) {
             const uint32_t n = base + t;
@@ -570,20 +573,19 @@ __device__ __forceinline__ void jump_pass(const uint32_t *__restrict__ r,
                 const int low = v & -v;
                 const int bit = low == 1 ? 0 : (low == 2 ? 1 : (low == 4 ? 2 : 3));
                 q[v] = q[v & (v - 1)] ^ w[bit];
-                planes[(v - 1) * JUMP_PL + t] = q[v];
+                planes[v * JUMP_PL + t] = q[v];
             }
         }
         __syncthreads();
         if (active) {
-            const uint32_t nw = (ch + 31) / 32;
             for (uint32_t cw = 0; cw < nw; ++cw) {
-                uint32_t bits = __builtin_amdgcn_readfirstlane(g[(i0 >> 5) + cw]);
+                uint32_t bits = __builtin_amdgcn_readlane(gv, cw);
                 if (cw == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
+                const uint32_t *col = planes + 32 * cw + lane;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const uint32_t v = (bits >> (4 * k)) & 15u;
-                    if (v == 0) continue;
-                    const uint32_t *src = planes + (v - 1) * JUMP_PL + 32 * cw + 4 * k + lane;
+                    const uint32_t *src = col + v * JUMP_PL + 4 * k;
 #pragma unroll
                     for (int j = 0; j < JA; ++j) acc[j] ^= src[64 * j];
                 }
@@ -605,6 +607,7 @@ jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n_blocks = (n_items + JUMP_WAVES - 1) / JUMP_WAVES;
+    for (uint32_t t = threadIdx.x; t < (uint32_t)JUMP_PL; t += 64 * JUMP_WAVES) planes[t] = 0u;
     for (uint32_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
         const JumpItem lead = items[blk * JUMP_WAVES];
         const uint32_t mine = blk * JUMP_WAVES + wave;
@@ -612,8 +615,8 @@ jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
         jit.out = 0;
         if (mine < n_items) jit = items[mine];
         const bool active = jit.out != 0;
-        const uint32_t *r = reinterpret_cast<const uint32_t *>(lead.raw) + 1;
-        const uint32_t *g = reinterpret_cast<const uint32_t *>(jit.poly);
+        gptr<const uint32_t> r = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(lead.raw)) + 1;
+        gptr<const uint32_t> g = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(jit.poly));
         uint32_t *out = reinterpret_cast<uint32_t *>(jit.out);
         const uint32_t D = lead.nbits, M = lead.m, rlen = lead.nbits + lead.m;
         for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
