@@ -352,6 +352,25 @@ struct Core {
         }
     }
 
+    // Whole steps of S = KE rows (the same S every step), then nothing:
+    // the caller finishes the partial last step.
+    template <bool F32, int KE>
+    static __device__ __forceinline__ void full_steps(const Step &p, uint32_t *__restrict__ buf,
+                                                      const uint32_t *__restrict__ tbl,
+                                                      gptr<uint32_t> gout, gptr<uint32_t> raw,
+                                                      bool want_raw, uint64_t n_steps,
+                                                      uint32_t S, uint32_t &h, uint64_t &done,
+                                                      uint32_t lane) {
+        for (uint64_t st = 0; st < n_steps; ++st) {
+            maybe_compact(buf, h, SMAX, lane);
+            body<F32, KE>(p, buf, tbl, gout + done + lane, raw + N + done + lane, want_raw, h,
+                          S, lane);
+            group_sync<TPS>();
+            h += S;
+            done += S;
+        }
+    }
+
     template <bool F32>
     static __device__ __forceinline__ void steps_wide(const Step &p, uint32_t *__restrict__ buf,
                                                       const uint32_t *__restrict__ tbl,
@@ -362,11 +381,23 @@ struct Core {
         // full steps: W rounded down to whole 128-byte lines when wide
         uint32_t smax = p.W >= 64 ? (p.W & ~31u) : p.W;
         if (smax > (uint32_t)SMAX) smax = SMAX;
-        while (done < count) {
-            const uint64_t rem = count - done;
-            const uint32_t S = rem < smax ? (uint32_t)rem : smax;
-            // lanes compute every word of their k < keff, so keep h + SMAX
-            // inside the buffer (words past S are rewritten before any read)
+        // lanes compute every word of their rows, so keep h + SMAX inside
+        // the buffer (words past S are rewritten before any read)
+        const uint64_t n_full = (count - done) / smax;
+        switch ((smax + TPS - 1) / TPS) {
+#define MTGP_FULL(KE)                                                                       \
+    case KE:                                                                                \
+        if constexpr (KE <= K)                                                              \
+            full_steps<F32, KE>(p, buf, tbl, gout, raw, want_raw, n_full, smax, h, done,   \
+                                lane);                                                      \
+        break;
+            MTGP_FULL(1) MTGP_FULL(2) MTGP_FULL(3) MTGP_FULL(4)
+            MTGP_FULL(5) MTGP_FULL(6) MTGP_FULL(7) MTGP_FULL(8)
+#undef MTGP_FULL
+            default: break;
+        }
+        if (done < count) {
+            const uint32_t S = (uint32_t)(count - done);
             maybe_compact(buf, h, SMAX, lane);
             gptr<uint32_t> o = gout + done + lane;
             gptr<uint32_t> rw = raw + N + done + lane;

@@ -18,7 +18,8 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libmtgp.so")
+# The in-tree build; MTGP_LIBRARY may name another build of the same sources.
+LIB_PATH = os.environ.get("MTGP_LIBRARY") or os.path.join(_HERE, "_build", "libmtgp.so")
 PARAM_WORDS = 53
 DEVICE_PARAM_BYTES = 4096
 U32, F32 = 0, 1
