@@ -569,21 +569,24 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
 // in LDS once, and every wave of the block reads them: per output word one
 // LDS read per nibble instead of one per set bit.  Plane 0 stays zero, so
 // the lookups are branch-free and several nibbles' reads are in flight.
+// Lane l owns output words 4l..4l+3 (+256 j) of a pass and reads them as one
+// 16-byte LDS access per nibble (4c + 4l is a multiple of 4).
 constexpr int JUMP_WAVES = JUMP_BLOCK;
-constexpr int JUMP_CH = 512;    // coefficients per chunk (multiple of 32)
+constexpr int JUMP_CH = 256;    // coefficients per chunk (multiple of 32)
 constexpr int JUMP_JA = 8;      // output words per lane per pass
 constexpr int JUMP_MT = 64 * JUMP_JA;
 constexpr int JUMP_PL = JUMP_CH + JUMP_MT;  // plane length (words)
 constexpr int JUMP_LDS_BYTES = 16 * JUMP_PL * 4;
 
+typedef uint32_t jv4 __attribute__((ext_vector_type(4)));
 template <int JA>
 __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uint32_t> g,
                                           uint32_t *__restrict__ out, bool active, uint32_t D,
                                           uint32_t rlen, uint32_t m0, uint32_t mt,
                                           uint32_t *__restrict__ planes, uint32_t lane) {
-    uint32_t acc[JA];
+    jv4 acc[JA];
 #pragma unroll
-    for (int j = 0; j < JA; ++j) acc[j] = 0;
+    for (int j = 0; j < JA; ++j) acc[j] = jv4{0u, 0u, 0u, 0u};
     for (uint32_t i0 = 0; i0 < D; i0 += JUMP_CH) {
         const uint32_t ch = (D - i0) < (uint32_t)JUMP_CH ? (D - i0) : (uint32_t)JUMP_CH;
         const uint32_t L = ch + mt;
@@ -612,13 +615,14 @@ __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uin
             for (uint32_t cw = 0; cw < nw; ++cw) {
                 uint32_t bits = __builtin_amdgcn_readlane(gv, cw);
                 if (cw == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
-                const uint32_t *col = planes + 32 * cw + lane;
+                const uint32_t *col = planes + 32 * cw + 4 * lane;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const uint32_t v = (bits >> (4 * k)) & 15u;
                     const uint32_t *src = col + v * JUMP_PL + 4 * k;
 #pragma unroll
-                    for (int j = 0; j < JA; ++j) acc[j] ^= src[64 * j];
+                    for (int j = 0; j < JA; ++j)
+                        acc[j] ^= *reinterpret_cast<const jv4 *>(src + 256 * j);
                 }
             }
         }
@@ -626,8 +630,11 @@ __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uin
     if (active) {
 #pragma unroll
         for (int j = 0; j < JA; ++j) {
-            const uint32_t m = lane + 64 * j;
-            if (m < mt) out[m0 + m] = acc[j];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t m = 4 * lane + 256 * j + e;
+                if (m < mt) out[m0 + m] = acc[j][e];
+            }
         }
     }
 }
@@ -652,11 +659,10 @@ jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
         const uint32_t D = lead.nbits, M = lead.m, rlen = lead.nbits + lead.m;
         for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
             const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
-            switch ((mt + 63) / 64) {
+            switch ((mt + 255) / 256) {
 #define MTGP_JP(JA) \
     case JA: jump_pass<JA>(r, g, out, active, D, rlen, m0, mt, planes, lane); break;
-                MTGP_JP(1) MTGP_JP(2) MTGP_JP(3) MTGP_JP(4)
-                MTGP_JP(5) MTGP_JP(6) MTGP_JP(7) MTGP_JP(8)
+                MTGP_JP(1) MTGP_JP(2)
 #undef MTGP_JP
                 default: break;
             }
@@ -823,7 +829,8 @@ hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hip
         attr_set = true;
     }
     int grid = (int)((n_items + JUMP_WAVES - 1) / JUMP_WAVES);
-    const int cap = num_cus * 2;  // two blocks of 60 KB planes fit a CU's LDS
+    const int cap = num_cus * 3;  // three blocks of 48 KB planes fit a CU's LDS
+
     if (grid > cap) grid = cap;
     (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(jump_kernel, dim3(grid), dim3(64 * JUMP_WAVES), JUMP_LDS_BYTES, s, items,
