@@ -15,6 +15,11 @@ timing starts.
       dtype, one launch, against one launch per stream in order
   C5  serving: 16384 resident mexp-11213 streams, Poisson request traces at
       fractions of the saturation rate, against one launch per request
+  P1  10,000 mexp-3217 statuses sharing seed status 0, 2^20 each, plus the
+      duplicate check of their minimal polynomials
+  P2  100 mexp-3217 statuses x 100 random seeds, 2^20 each, same check
+  DEV the C3 batch through the device-side draw API (one workgroup of 256
+      threads per stream)
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -461,6 +466,119 @@ def run_c4(args):
                         "speedup_of_batch_vs_unsplit": round(b_plain[0] / ms_step, 2)}})
 
 
+def run_paper(args):
+    """The paper's experiment shapes as generation workloads (mexp 3217):
+    P1 10,000 statuses sharing seed status 0, P2 100 statuses x 100 random
+    seeds; 2^20 uint32 per stream in one batch launch, plus the duplicate
+    check of the streams' minimal polynomials."""
+    import numpy as np
+    import torch
+    from paper_1501_07701_amd import mtgp, workloads
+
+    name = args.workload
+    cfg = workloads.CONFIGS[name]
+    params, seeds = workloads.config_inputs(name)
+    n, count, mexp = params.shape[0], cfg["count"], cfg["mexp"]
+    N = mtgp.state_words(mexp)
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    items = [(k, mtgp.U32, count, out.data_ptr() + 4 * k * count) for k in range(n)]
+    arr = mtgp.make_work(items)
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    ws = g.workspace(items)
+    t_plan = time.perf_counter() - t0
+
+    def step(record):
+        g.reseed()
+        pr = _pair(torch, stream) if record else None
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, arr, ws)
+        if record:
+            pr[1].record(stream)
+            return [pr]
+        return []
+
+    log("timing ...")
+    ms_step, ms_launch = _timed_steps(torch, step, args.warmup, args.steps)
+    if mtgp.batch_errors(ws):
+        log("jump-ahead segment checks failed")
+        sys.exit(3)
+    log("stream polynomials ...")
+    t0 = time.perf_counter()
+    deg, co = mtgp.stream_polynomials(g.d_params, n, mexp)
+    t_poly = time.perf_counter() - t0
+    if name == "P2":
+        # one polynomial per parameter set: seeds must not change it
+        per_set = deg.reshape(cfg["param_sets"], cfg["seeds"])
+        seed_invariant = bool((per_set == per_set[:, :1]).all())
+    else:
+        seed_invariant = None
+    keys = {co[k].tobytes() for k in range(n) if deg[k] > 0}
+    distinct_expected = cfg["param_sets"] if name == "P2" else n
+    fill = _fill_gbps(torch, mtgp, out, stream)
+    alg = n * count * 4 + n * (8 * N + 256)
+    cpu = None
+    if not args.no_cpu_baseline:
+        th, c = _threads(), 1 << 16
+        log("cpu baseline ...")
+        cv, dt = cpu_sample(params, seeds, [c] * n, [0] * n, th)
+        cpu = {"value": round(cv, 4), "unit": "G uint32/s", "cores": th, "kind": "oracle",
+               "sample": "all %d streams x 2^16 uint32 outputs from the seeded states, "
+                         "%.2f s wall on %d threads" % (n, dt, th)}
+    return _common(args, n * count / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
+                   {"workload": cfg["name"], "mexp": mexp, "streams": n,
+                    "outputs_per_stream": count, "passes": ["u32"]},
+                   alg / (ms_launch * 1e-3) / 1e9, cpu,
+                   {"avg_generate_launch_ms": round(ms_launch, 3),
+                    "store_only_fill_GBps": round(fill, 1),
+                    "plan_build_s": round(t_plan, 2),
+                    "polynomials": {"seconds": round(t_poly, 2),
+                                    "unverified": int((deg < 0).sum()),
+                                    "degree_min": int(deg.max(initial=0) if (deg < 0).all()
+                                                      else deg[deg > 0].min()),
+                                    "degree_max": int(deg.max()),
+                                    "distinct": len(keys),
+                                    "distinct_expected": distinct_expected,
+                                    "seed_invariant": seed_invariant}})
+
+
+def run_device_api(args):
+    """The device-side draw API (one workgroup per stream, 256 threads
+    drawing 256 outputs per call) on the 4096 x 2^20 mexp-23209 batch."""
+    import numpy as np
+    import torch
+    from paper_1501_07701_amd import mtgp, workloads
+
+    cfg = workloads.CONFIGS["C3"]
+    params, seeds = workloads.config_inputs("C3")
+    n, count, mexp = params.shape[0], cfg["count"], cfg["mexp"]
+    N = mtgp.state_words(mexp)
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(record):
+        g.reseed()
+        pr = _pair(torch, stream) if record else None
+        mtgp.generate_workgroup(g.d_params, g.d_states, g.stride, n, count, out, mtgp.U32, 256)
+        if record:
+            pr[1].record(stream)
+            return [pr]
+        return []
+
+    log("timing ...")
+    ms_step, ms_launch = _timed_steps(torch, step, args.warmup, args.steps)
+    alg = n * count * 4 + n * (8 * N + 256)
+    W = N - params[:, 1].astype(np.int64)
+    return _common(args, n * count / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
+                   {"workload": cfg["name"] + "_device_api", "mexp": mexp, "streams": n,
+                    "outputs_per_stream": count, "threads_per_workgroup": 256},
+                   alg / (ms_launch * 1e-3) / 1e9, None,
+                   {"avg_generate_launch_ms": round(ms_launch, 3),
+                    "critical_path_draws": int(-(-count // 256)),
+                    "min_step_width": int(W.min())})
+
+
 def _serve(mtgp, srv, trace, n, scale):
     """Submits the first n requests of `trace` at their arrival times
     (t_arrival * scale seconds after the start) and collects them.
@@ -598,7 +716,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C4", "C5"])
+    ap.add_argument("--workload", default="C2",
+                    choices=["C2", "C3", "C4", "C5", "P1", "P2", "DEV"])
     ap.add_argument("--requests", type=int, default=2000,
                     help="C5: requests per arrival rate")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -616,7 +735,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    run = {"C2": run_c2, "C3": run_c3, "C4": run_c4, "C5": run_c5}[args.workload]
+    run = {"C2": run_c2, "C3": run_c3, "C4": run_c4, "C5": run_c5, "P1": run_paper,
+           "P2": run_paper, "DEV": run_device_api}[args.workload]
     line = run(args)
     print(json.dumps(line), flush=True)
 

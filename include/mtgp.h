@@ -227,6 +227,33 @@ int mtgp_state_import(const void *d_params, uint32_t *d_states,
                       int state_stride, int n_streams, const uint32_t *h_in,
                       void *stream);
 
+/* Generation through the device-side draw API of mtgp_device.h: one
+ * workgroup of `threads` threads (a multiple of 64 in [64, 1024]) per stream
+ * keeps the stream's state in LDS and draws `threads` outputs per call
+ * (the paper's per-block consumer, Sec. 2 and Sec. 3.2).  Same outputs,
+ * layout (out[k * count + j]) and state advance as mtgp_generate_u32/f32
+ * for dtype MTGP_U32/MTGP_F32; it also serves as the reference user of that
+ * API.  MTGP_EINVAL on a bad argument. */
+int mtgp_generate_workgroup(const void *d_params, uint32_t *d_states,
+                            int state_stride, int n_streams,
+                            uint64_t count_per_stream, int dtype, int threads,
+                            void *d_out, void *stream);
+
+/* Minimal polynomial of each stream's output word sequence from its seed
+ * status (the polynomial the jump-ahead uses; Berlekamp-Massey on the host,
+ * checked on the device to annihilate the word sequence).  For parameter
+ * sets from the Dynamic Creator it is the characteristic polynomial of the
+ * generator, whose uniqueness across a set is what makes the streams
+ * distinct (Sec. 3.2): equal polynomials flag duplicate generators.
+ * Streams [0, n_streams): h_degrees[k] = degree (<= mexp), or -1 when no
+ * polynomial could be verified; h_coeffs[k * words_per_stream ..] holds the
+ * coefficients, bit i (word i/32, bit i%32) = coefficient of x^i,
+ * words_per_stream >= mexp/32 + 1.  Synchronous (runs device work on
+ * `stream`; the result is cached per parameter set). */
+int mtgp_stream_polynomials(const void *d_params, int n_streams,
+                            uint32_t *h_coeffs, int words_per_stream,
+                            int *h_degrees, void *stream);
+
 /* Store-only fill of n words (bandwidth reference for the roofline). */
 int mtgp_fill_u32(uint32_t *d_out, uint64_t n_words, uint32_t value,
                   void *stream);

@@ -443,6 +443,26 @@ int mtgp_state_import(const void *d_params, uint32_t *d_states, int state_stride
     return e == hipSuccess ? MTGP_OK : hip_fail(e, "hipStreamSynchronize(import)");
 }
 
+int mtgp_generate_workgroup(const void *d_params, uint32_t *d_states, int state_stride,
+                            int n_streams, uint64_t count_per_stream, int dtype, int threads,
+                            void *d_out, void *stream) {
+    auto ps = lookup_params(d_params, n_streams);
+    if (!ps) return MTGP_EINVAL;
+    if (n_streams <= 0) return fail(MTGP_EINVAL, "n_streams=%d", n_streams);
+    if (!d_states || state_stride < ps->N)
+        return fail(MTGP_EINVAL, "state_stride %d < N=%d or NULL states", state_stride, ps->N);
+    if (dtype != MTGP_U32 && dtype != MTGP_F32) return fail(MTGP_EINVAL, "dtype %d", dtype);
+    if (threads < 64 || threads > 1024 || (threads & 63))
+        return fail(MTGP_EINVAL, "threads %d: a multiple of 64 in [64, 1024]", threads);
+    if (count_per_stream == 0) return MTGP_OK;
+    if (!d_out) return fail(MTGP_EINVAL, "d_out is NULL");
+    hipError_t e = launch_workgroup((const uint32_t *)d_params, d_states, (uint32_t)state_stride,
+                                    (uint32_t)n_streams, count_per_stream, (uint32_t *)d_out,
+                                    dtype == MTGP_F32 ? 1u : 0u, (uint32_t)threads,
+                                    (uint32_t)ps->N, (hipStream_t)stream);
+    return e == hipSuccess ? MTGP_OK : hip_fail(e, "workgroup kernel");
+}
+
 int mtgp_fill_u32(uint32_t *d_out, uint64_t n_words, uint32_t value, void *stream) {
     if (!d_out || ((uintptr_t)d_out & 15u)) return fail(MTGP_EINVAL, "d_out must be 16-byte aligned");
     if (n_words == 0) return MTGP_OK;

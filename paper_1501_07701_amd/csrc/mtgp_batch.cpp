@@ -778,6 +778,36 @@ extern "C" {
 
 size_t mtgp_batch_workspace_bytes(int n_items) { return batch_min_ws_bytes(n_items); }
 
+int mtgp_stream_polynomials(const void *d_params, int n_streams, uint32_t *h_coeffs,
+                            int words_per_stream, int *h_degrees, void *stream) {
+    auto ps = lookup_params(d_params, n_streams);
+    if (!ps) return MTGP_EINVAL;
+    if (n_streams <= 0 || n_streams > ps->n)
+        return fail(MTGP_EINVAL, "n_streams %d outside [1, %d]", n_streams, ps->n);
+    if (!h_coeffs || !h_degrees) return fail(MTGP_EINVAL, "NULL output array");
+    const int need = (int)ps->mexp / 32 + 1;
+    if (words_per_stream < need)
+        return fail(MTGP_EINVAL, "words_per_stream %d < %d", words_per_stream, need);
+    std::vector<int> all((size_t)n_streams);
+    for (int k = 0; k < n_streams; ++k) all[(size_t)k] = k;
+    int rc = ensure_jumps(ps, d_params, all, tuning_for(ps->N), (hipStream_t)stream);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(ps->jump_mu);
+    for (int k = 0; k < n_streams; ++k) {
+        uint32_t *dst = h_coeffs + (size_t)k * (size_t)words_per_stream;
+        std::memset(dst, 0, (size_t)words_per_stream * 4);
+        const StreamJump *sj = ps->jumps[(size_t)k].get();
+        if (!sj || sj->status != 1) {
+            h_degrees[k] = -1;
+            continue;
+        }
+        h_degrees[k] = sj->D;
+        const std::vector<uint32_t> w = pack32(sj->mod->p, sj->D + 1);
+        std::memcpy(dst, w.data(), std::min(w.size(), (size_t)words_per_stream) * 4);
+    }
+    return MTGP_OK;
+}
+
 int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items, int n_items,
                                size_t *bytes) {
     if (!bytes) return fail(MTGP_EINVAL, "bytes is NULL");

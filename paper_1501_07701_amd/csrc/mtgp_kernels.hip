@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mtgp_device.h"
 #include "mtgp_internal.hpp"
 
 namespace mtgp {
@@ -851,6 +852,52 @@ hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride
 hipError_t launch_reset(uint32_t *counter, hipStream_t s) {
     (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+// The device API reads the same parameter blocks the library writes.
+static_assert(MTGP_DP_N == P_N && MTGP_DP_POS == P_POS && MTGP_DP_SH1 == P_SH1 &&
+                  MTGP_DP_SH2 == P_SH2 && MTGP_DP_MASK == P_MASK && MTGP_DP_REC == P_REC &&
+                  MTGP_DP_TMP == P_TMP && MTGP_DP_FLT == P_FLT && MTGP_DP_WORDS == P_WORDS,
+              "device API parameter layout");
+
+// Generation through the device-side draw API: workgroup k owns stream k and
+// writes count outputs at out + k*count, drawing blockDim.x at a time.
+__global__ void __launch_bounds__(1024)
+workgroup_kernel(const uint32_t *__restrict__ params, uint32_t *__restrict__ states,
+                 uint32_t stride, uint64_t count, uint32_t *__restrict__ out, uint32_t f32,
+                 uint32_t lds_words) {
+    extern __shared__ uint32_t lds[];
+    mtgp_device_stream s;
+    const uint32_t k = blockIdx.x;
+    uint32_t *row = states + (uint64_t)k * stride;
+    mtgp_device_begin(s, params, k, row, lds, lds_words);
+    gptr<uint32_t> o = (gptr<uint32_t>)(out + (uint64_t)k * count);
+    for (uint64_t done = 0; done < count; done += blockDim.x) {
+        const uint64_t rem = count - done;
+        const uint32_t n = rem < blockDim.x ? (uint32_t)rem : blockDim.x;
+        const uint32_t r = f32 ? mtgp_device_draw_bits<true>(s, n)
+                               : mtgp_device_draw_bits<false>(s, n);
+        if (threadIdx.x < n) o[done + threadIdx.x] = r;
+    }
+    mtgp_device_end(s, row);
+}
+
+hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t stride,
+                            uint32_t n_streams, uint64_t count, uint32_t *out, uint32_t f32,
+                            uint32_t threads, uint32_t n_words, hipStream_t s) {
+    const uint32_t words = MTGP_DEVICE_LDS_WORDS(n_words, threads);
+    static bool attr_set = false;  // benign race: idempotent attribute
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)workgroup_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)MTGP_DEVICE_LDS_WORDS(1391u, 1024u) * 4);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(workgroup_kernel, dim3(n_streams), dim3(threads), (size_t)words * 4, s,
+                       params, states, stride, count, out, f32, words);
     return hipGetLastError();
 }
 

@@ -90,6 +90,10 @@ _SIGS = {
                        ctypes.POINTER(ctypes.c_float), ctypes.c_int], ctypes.c_int),
     "mtgp_state_export": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
     "mtgp_state_import": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_generate_workgroup": ([_VP, _VP, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_stream_polynomials": ([_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, _VP],
+                                ctypes.c_int),
     "mtgp_fill_u32": ([_VP, ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "mtgp_server_create": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_uint64,
                             ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)],
@@ -302,6 +306,27 @@ def state_import(d_params, d_states, stride: int, host_states: np.ndarray, strea
     h = np.ascontiguousarray(host_states, dtype=np.uint32)
     _check(lib().mtgp_state_import(_ptr(d_params), _ptr(d_states), stride, h.shape[0], _ptr(h),
                                    _stream(stream)), "mtgp_state_import")
+
+
+def generate_workgroup(d_params, d_states, stride: int, n_streams: int, count: int, d_out,
+                       dtype: int = U32, threads: int = 256, stream=None) -> None:
+    """Generation through the device-side draw API (one workgroup per
+    stream); out[k * count + j] as for generate()."""
+    _check(lib().mtgp_generate_workgroup(_ptr(d_params), _ptr(d_states), stride, n_streams,
+                                         count, dtype, threads, _ptr(d_out), _stream(stream)),
+           "mtgp_generate_workgroup")
+
+
+def stream_polynomials(d_params, n_streams: int, mexp: int, stream=None):
+    """(degrees (n,) int32, coefficients (n, mexp//32+1) uint32): the
+    minimal polynomial of each stream's output sequence from its seed."""
+    words = mexp // 32 + 1
+    coeffs = np.zeros((n_streams, words), dtype=np.uint32)
+    degrees = np.zeros(n_streams, dtype=np.int32)
+    _check(lib().mtgp_stream_polynomials(_ptr(d_params), n_streams, coeffs.ctypes.data, words,
+                                         degrees.ctypes.data, _stream(stream)),
+           "mtgp_stream_polynomials")
+    return degrees, coeffs
 
 
 def fill_u32(d_out, n_words: int, value: int, stream=None) -> None:

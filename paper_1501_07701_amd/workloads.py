@@ -146,6 +146,15 @@ CONFIGS = {
     "C5": dict(name="mtgp11213_serve_16384_resident", mexp=11213,
                streams=16384, len_log2=(8, 24), p_float=0.5,
                pool_bytes=64 * 10**9, master=0xC0FFEE05),
+    # shapes of the paper's experiments: 10,000 statuses of period 2^3217
+    # sharing seed status 0 (Sec. 4.1), and 100 statuses x 100 random seeds
+    # (Random Spacing, Sec. 5.1); random parameter sets stand in for the
+    # Dynamic Creator's
+    "P1": dict(name="mtgp3217_10000_statuses_seed0_2^20", mexp=3217, streams=10000,
+               count=1 << 20, dtypes=("u32",), master=0xC0FFEE06),
+    "P2": dict(name="mtgp3217_100_statuses_x_100_seeds_2^20", mexp=3217, streams=10000,
+               param_sets=100, seeds=100, count=1 << 20, dtypes=("u32",),
+               master=0xC0FFEE07),
 }
 
 
@@ -153,6 +162,14 @@ def config_inputs(cfg: str, n_streams: int | None = None):
     """(params, seeds) for a workload, optionally only its first n streams."""
     c = CONFIGS[cfg]
     n = c["streams"] if n_streams is None else n_streams
+    if cfg == "P1":      # every status seeded with 0
+        return make_params(c["mexp"], n, c["master"]), np.zeros(n, dtype=np.uint32)
+    if cfg == "P2":      # stream a*n_seeds + b: parameter set a, seed b
+        n_par, n_seed = c["param_sets"], c["seeds"]
+        par = np.repeat(make_params(c["mexp"], n_par, c["master"]), n_seed, axis=0)
+        seeds = (splitmix64(np.arange(n_seed, dtype=np.uint64), c["master"] ^ 0x5EED)
+                 >> np.uint64(32)).astype(np.uint32)
+        return par[:n], np.tile(seeds, n_par)[:n]
     return make_params(c["mexp"], n, c["master"]), make_seeds(n)
 
 
