@@ -287,6 +287,13 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states,
  * exceed the pool, MTGP_EAGAIN if the queue is full. Thread-safe. */
 int mtgp_submit(mtgp_server *srv, int32_t stream_id, uint64_t count,
                 int dtype, uint64_t *ticket);
+/* Queue n requests at once (stream_ids[i], counts[i], dtypes[i]; tickets[i]
+ * receives each ticket), in order, as n mtgp_submit calls would; all or
+ * none: every request is validated first, MTGP_EAGAIN if the queue lacks
+ * room for all of them.  Thread-safe. */
+int mtgp_submit_many(mtgp_server *srv, const int32_t *stream_ids,
+                     const uint64_t *counts, const int *dtypes, int n,
+                     uint64_t *tickets);
 /* Non-blocking status; *d_result is the device address of the output once
  * MTGP_DONE (valid until mtgp_release). */
 int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state,

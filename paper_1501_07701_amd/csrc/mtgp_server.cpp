@@ -202,7 +202,10 @@ struct Server {
         }
     }
 
-    int launch_locked(int si) {
+    // Called with `lk` held; releases it while the batch is planned and
+    // launched (only this thread touches the slot and the launched items'
+    // records meanwhile), so submissions and polls do not wait on planning.
+    int launch_locked(int si, std::unique_lock<std::mutex> &lk) {
         Slot &sl = slots[si];
         const int n = (int)ready.size();
         std::vector<mtgp::Request> work((size_t)n);
@@ -232,11 +235,13 @@ struct Server {
         sl.n_done = 0;
         sl.busy = true;
         int rc;
+        lk.unlock();
         {
-            std::lock_guard<std::mutex> lk(sl.stage->mu);
+            std::lock_guard<std::mutex> sg(sl.stage->mu);
             rc = run_batch(ps, d_params, d_states, stride, work, sl.d_ws, ws_bytes, sl.hs,
                            tuning_for(ps->N), false, *sl.stage);
         }
+        lk.lock();
         if (rc == MTGP_OK) {
             hipError_t e = hipEventRecord(sl.done, sl.hs);
             if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord(slot)");
@@ -327,7 +332,7 @@ struct Server {
                 const bool full = (int)ready.size() >= opts.max_batch_items;
                 const bool waited = now() - ready_since >= opts.batch_window_ns;
                 if (free_slot >= 0 && (busy_slots == 0 || full || waited)) {
-                    (void)launch_locked(free_slot);
+                    (void)launch_locked(free_slot, lk);
                     ready_since = 0;
                     cv_done.notify_all();
                     continue;
@@ -455,6 +460,45 @@ int mtgp_submit(mtgp_server *srv, int32_t stream_id, uint64_t count, int dtype,
     S.reqs.emplace(r.ticket, r);
     ++S.queued;
     *ticket = r.ticket;
+    S.cv_work.notify_one();
+    return MTGP_OK;
+}
+
+int mtgp_submit_many(mtgp_server *srv, const int32_t *stream_ids, const uint64_t *counts,
+                     const int *dtypes, int n, uint64_t *tickets) {
+    if (!srv || n < 0 || (n > 0 && (!stream_ids || !counts || !dtypes || !tickets)))
+        return fail(MTGP_EINVAL, "NULL argument or n=%d", n);
+    Server &S = srv->s;
+    for (int i = 0; i < n; ++i) {
+        if (stream_ids[i] < 0 || stream_ids[i] >= S.n_streams)
+            return fail(MTGP_EINVAL, "request %d: stream %d outside [0, %d)", i, stream_ids[i],
+                        S.n_streams);
+        if (dtypes[i] != MTGP_U32 && dtypes[i] != MTGP_F32)
+            return fail(MTGP_EINVAL, "request %d: dtype %d", i, dtypes[i]);
+        if (counts[i] == 0) return fail(MTGP_EINVAL, "request %d: count must be > 0", i);
+    }
+    std::lock_guard<std::mutex> lk(S.mu);
+    for (int i = 0; i < n; ++i)
+        if (counts[i] * 4 > S.pool->size())
+            return fail(MTGP_ETOOBIG, "request %d of %llu bytes exceeds the %llu-byte pool", i,
+                        (unsigned long long)(counts[i] * 4),
+                        (unsigned long long)S.pool->size());
+    if (S.stop) return fail(MTGP_ECANCELED, "server is shutting down");
+    if ((int)S.queued + n > S.opts.max_queue) return fail(MTGP_EAGAIN, "queue full");
+    const uint64_t t = S.now();
+    for (int i = 0; i < n; ++i) {
+        Req r;
+        r.ticket = S.next_ticket++;
+        r.stream = stream_ids[i];
+        r.count = counts[i];
+        r.dtype = dtypes[i];
+        r.t_submit = t;
+        S.per_stream[r.stream].push_back(r.ticket);
+        S.pending.push_back(r.ticket);
+        tickets[i] = r.ticket;
+        S.reqs.emplace(r.ticket, r);
+        ++S.queued;
+    }
     S.cv_work.notify_one();
     return MTGP_OK;
 }

@@ -99,6 +99,7 @@ _SIGS = {
                             ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)],
                            ctypes.c_int),
     "mtgp_submit": ([_VP, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _U64P], ctypes.c_int),
+    "mtgp_submit_many": ([_VP, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
     "mtgp_poll": ([_VP, ctypes.c_uint64, _INTP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "mtgp_wait": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "mtgp_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
@@ -421,6 +422,16 @@ class Server:
         _check(lib().mtgp_submit(self.h, int(stream_id), int(count), int(dtype),
                                  ctypes.byref(t)), "mtgp_submit")
         return int(t.value)
+
+    def submit_many(self, stream_ids, counts, dtypes) -> np.ndarray:
+        """Queues all requests in one call; returns their tickets."""
+        st = np.ascontiguousarray(stream_ids, dtype=np.int32)
+        ct = np.ascontiguousarray(counts, dtype=np.uint64)
+        dt = np.ascontiguousarray(dtypes, dtype=np.int32)
+        tk = np.zeros(st.shape[0], dtype=np.uint64)
+        _check(lib().mtgp_submit_many(self.h, st.ctypes.data, ct.ctypes.data, dt.ctypes.data,
+                                      int(st.shape[0]), tk.ctypes.data), "mtgp_submit_many")
+        return tk
 
     def poll(self, ticket: int):
         st = ctypes.c_int()
