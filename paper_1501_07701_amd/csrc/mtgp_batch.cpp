@@ -340,6 +340,17 @@ static uint64_t effective_target(const ParamSet &ps, const std::vector<Request> 
     return std::max<uint64_t>((uint64_t)t.jump_target_steps, adaptive);
 }
 
+// Segment length for a target of v outputs: v rounded down to m * 2^e with
+// m in {4, 5, 6, 7} (at most 20% short), at least 256.  The coarse grid
+// keeps a stream's segment length, and so its cached jump polynomials, the
+// same from batch to batch when the target moves a little; whole 256-word
+// multiples keep every segment's stores line-aligned.
+static uint64_t segment_length(uint64_t v) {
+    if (v < 1024) return std::max<uint64_t>(256, v / 256 * 256);
+    const int e = 63 - __builtin_clzll(v) - 2;  // v / 2^e in [4, 8), e >= 8
+    return (v >> e) << e;
+}
+
 // Splits a request when it needs more than T dependent steps and the
 // stream's jump data is usable.
 static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_t T,
@@ -350,8 +361,7 @@ static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_
     const uint64_t so = step_outputs(ps, r.stream, t);
     if ((r.count + so - 1) / so <= T) return;
     const uint64_t P = (uint64_t)sj->D + 1;
-    // whole 256-word blocks keep every segment's stores line-aligned
-    const uint64_t lseg = std::max<uint64_t>(256, T * so / 256 * 256);
+    const uint64_t lseg = segment_length(T * so);
     const uint64_t c0 = (P + 1 + lseg - 1) / lseg;   // segment 0 keeps >= 1 output past P
     const uint64_t cend = (r.count + lseg - 1) / lseg;
     if (cend <= c0) return;
