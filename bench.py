@@ -586,52 +586,12 @@ def run_device_api(args):
                     "min_step_width": int(W.min())})
 
 
-def _serve(mtgp, srv, trace, n, scale):
-    """Submits the first n requests of `trace` at their arrival times
-    (t_arrival * scale seconds after the start; requests that came due
-    together go in one submission call) and collects them after the last
-    submission (the pool holds every result, so nothing waits on a release).
-    Returns (latency ns, completion ns, per-request stage ns
-    [queued, admitted, running]), measured from the scheduled arrival: the
-    server's own submit-to-done time plus how late the submission was."""
-    import numpy as np
-    arr_ns = trace["t_arrival"][:n] * scale * 1e9
-    st, L, dt = trace["stream"], trace["length"], trace["dtype"]
-    sub_ns = np.zeros(n)
-    tks = np.zeros(n, dtype=np.uint64)
-    i = 0
-    t0 = time.monotonic_ns()
-    while i < n:
-        now = time.monotonic_ns() - t0
-        j = i
-        while j < n and arr_ns[j] <= now:
-            j += 1
-        if j > i:
-            sub_ns[i:j] = now
-            tks[i:j] = srv.submit_many(st[i:j], L[i:j], dt[i:j])
-            i = j
-        else:
-            time.sleep(min(max((arr_ns[i] - now) * 1e-9, 0.0), 1e-4))
-    lat = np.zeros(n)
-    fin = np.zeros(n)
-    stages = np.zeros((n, 3))
-    for j in range(n):
-        tk = int(tks[j])
-        srv.wait(tk, 120 * 10**9)
-        ts, ta, tl, td = srv.times(tk)
-        fin[j] = sub_ns[j] + (td - ts)
-        lat[j] = fin[j] - arr_ns[j]
-        stages[j] = (ta - ts, tl - ta, td - tl)
-        srv.release(tk)
-    return lat, fin, stages
-
-
 def run_c5(args):
     """Serving: 16384 resident mexp-11213 streams; Poisson arrivals of
     requests with log-uniform lengths in [2^8, 2^24] and mixed dtype at
-    fractions of the saturation rate; p50/p99 latency (arrival to the
-    server's completion stamp) against one launch per request served FIFO
-    on one HIP stream."""
+    fractions of the saturation rate, replayed by the library's native trace
+    replay; p50/p99 latency (scheduled arrival to completion) against one
+    launch per request served FIFO on one HIP stream."""
     import numpy as np
     import torch
     from paper_1501_07701_amd import mtgp, workloads
@@ -644,30 +604,35 @@ def run_c5(args):
     lo, hi = cfg["len_log2"]
     trace = workloads.request_trace(n_req, 1.0, n_streams, len_log2=(lo, hi),
                                     p_float=cfg["p_float"], master=cfg["master"])
-    mean_L = float(trace["length"].mean())
+    L = trace["length"].astype(np.uint64)
+    st, dt = trace["stream"], trace["dtype"]
+    total = float(L.sum())
     srv = mtgp.Server(g, cfg["pool_bytes"], inflight=4, max_batch_items=512,
                       batch_window_ns=50_000, workspace_bytes_per_batch=128 << 20)
     try:
-        # saturation: every request arrives at once (also builds the
-        # jump-ahead data of the streams the trace touches)
-        log("saturation run ...")
-        _serve(mtgp, srv, trace, n_req, 0.0)
-        log("saturation run 2 ...")
-        _, fin, _ = _serve(mtgp, srv, trace, n_req, 0.0)
-        sat_outputs_s = float(trace["length"][:n_req].sum()) / (fin.max() * 1e-9)
-        lam_sat = sat_outputs_s / mean_L
+        # saturation: every request arrives at once (the first pass also
+        # builds the jump-ahead data of the streams the trace touches)
+        zero = np.zeros(n_req, dtype=np.uint64)
+        log("saturation pass 1 ...")
+        srv.replay(zero, st, L, dt)
+        log("saturation pass 2 ...")
+        lat0, _ = srv.replay(zero, st, L, dt)
+        sat_outputs_s = total / (float(lat0.max()) * 1e-9)
+        lam_sat = sat_outputs_s / float(L.mean())
         rates = []
         for f in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
             lam = f * lam_sat
             log("rate %.2f x saturation (%.0f req/s) ..." % (f, lam))
-            lat, fin, stg = _serve(mtgp, srv, trace, n_req, 1.0 / lam)
+            arr = (trace["t_arrival"] / lam * 1e9).astype(np.uint64)
+            lat, stg = srv.replay(arr, st, L, dt)
+            span = float((arr.astype(np.float64) + lat).max()) * 1e-9
             rates.append({"frac": f, "req_per_s": round(lam, 1),
                           "p50_ms": round(float(np.percentile(lat, 50)) * 1e-6, 3),
                           "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
-                          "p50_ms_queue_admit_run": [round(float(np.percentile(stg[:, c], 50))
-                                                           * 1e-6, 3) for c in range(3)],
-                          "served_G_per_s": round(float(trace["length"][:n_req].sum())
-                                                  / (fin.max() * 1e-9) / 1e9, 3)})
+                          "p50_ms_queued_admitted_running": [
+                              round(float(np.percentile(stg[:, c], 50)) * 1e-6, 3)
+                              for c in range(3)],
+                          "served_G_per_s": round(total / span / 1e9, 3)})
     finally:
         srv.close()
 
@@ -676,18 +641,17 @@ def run_c5(args):
     # then queued at the same arrival times
     log("one launch per request ...")
     nb = min(n_req, 1000)
-    buf = torch.empty(int(trace["length"][:nb].max()), dtype=torch.int32, device="cuda")
+    buf = torch.empty(int(L[:nb].max()), dtype=torch.int32, device="cuda")
     w1 = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
     d = np.zeros(nb)
     for i in range(nb):
-        it = [(int(trace["stream"][i]), int(trace["dtype"][i]), int(trace["length"][i]),
-               buf.data_ptr())]
+        it = [(int(st[i]), int(dt[i]), int(L[i]), buf.data_ptr())]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mtgp.generate_batch(g.d_params, g.d_states, g.stride, it, w1)
         torch.cuda.synchronize()
         d[i] = time.perf_counter() - t0
-    base_outputs_s = float(trace["length"][:nb].sum()) / d.sum()
+    base_outputs_s = float(L[:nb].sum()) / d.sum()
     for r in rates:
         arr = trace["t_arrival"][:nb] / r["req_per_s"]
         fin_t = np.zeros(nb)
@@ -700,7 +664,7 @@ def run_c5(args):
         r["one_launch_per_request_p99_ms"] = round(float(np.percentile(lat, 99)) * 1e3, 3)
     line = _common(args, sat_outputs_s / 1e9, "G outputs/s", 0.0,
                    {"workload": cfg["name"], "mexp": mexp, "resident_streams": n_streams,
-                    "requests_per_rate": n_req, "mean_request_outputs": round(mean_L)},
+                    "requests_per_rate": n_req, "mean_request_outputs": round(float(L.mean()))},
                    None, None,
                    {"saturation_req_per_s": round(lam_sat, 1),
                     "one_launch_per_request_G_per_s": round(base_outputs_s / 1e9, 3),
@@ -710,6 +674,7 @@ def run_c5(args):
     line["warmup"] = 0
     return line
 
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -718,7 +683,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C2",
                     choices=["C2", "C3", "C4", "C5", "P1", "P2", "DEV"])
-    ap.add_argument("--requests", type=int, default=2000,
+    ap.add_argument("--requests", type=int, default=20000,
                     help="C5: requests per arrival rate")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")

@@ -302,6 +302,17 @@ int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state,
 int mtgp_wait(mtgp_server *srv, uint64_t ticket, uint64_t timeout_ns);
 /* Return the request's output bytes to the pool and forget the ticket. */
 int mtgp_release(mtgp_server *srv, uint64_t ticket);
+/* Trace replay for serving measurements: submits request i (stream_ids[i],
+ * counts[i], dtypes[i]) t_arrival_ns[i] after the call starts (arrivals
+ * non-decreasing) from the calling thread, returns each result's pool
+ * bytes as soon as it completes, and blocks until all are done.
+ * h_latency_ns[i] = completion - scheduled arrival; h_stages_ns (3n, may be
+ * NULL) = queued, admitted-to-launch and running time of each request.
+ * The results themselves are not kept. */
+int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns,
+                       const int32_t *stream_ids, const uint64_t *counts,
+                       const int *dtypes, int n, uint64_t *h_latency_ns,
+                       uint64_t *h_stages_ns);
 /* Per-request timestamps in ns since server creation: submitted, admitted
  * (pool bytes granted), launched, completed (observed by the server). */
 int mtgp_request_times(mtgp_server *srv, uint64_t ticket, uint64_t *t_submit,

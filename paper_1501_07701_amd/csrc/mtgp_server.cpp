@@ -528,6 +528,78 @@ int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state, const void **d_resu
     }
 }
 
+int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int32_t *stream_ids,
+                       const uint64_t *counts, const int *dtypes, int n, uint64_t *h_latency_ns,
+                       uint64_t *h_stages_ns) {
+    if (!srv || n < 0 || (n > 0 && (!t_arrival_ns || !stream_ids || !counts || !dtypes ||
+                                    !h_latency_ns)))
+        return fail(MTGP_EINVAL, "NULL argument or n=%d", n);
+    Server &S = srv->s;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0 && t_arrival_ns[i] < t_arrival_ns[i - 1])
+            return fail(MTGP_EINVAL, "arrival %d before arrival %d", i, i - 1);
+        if (stream_ids[i] < 0 || stream_ids[i] >= S.n_streams || counts[i] == 0 ||
+            (dtypes[i] != MTGP_U32 && dtypes[i] != MTGP_F32) || counts[i] * 4 > S.pool->size())
+            return fail(MTGP_EINVAL, "request %d: bad stream, count or dtype", i);
+    }
+    const uint64_t start = S.now();
+    std::vector<uint64_t> tickets((size_t)n, 0);
+    std::vector<int> open;  // submitted, not yet finished
+    int next = 0, finished = 0;
+    while (finished < n) {
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            if (S.stop) return fail(MTGP_ECANCELED, "server is shutting down");
+            const uint64_t t = S.now();
+            bool queued_any = false;
+            while (next < n && start + t_arrival_ns[next] <= t &&
+                   (int)S.queued < S.opts.max_queue) {
+                Req r;
+                r.ticket = S.next_ticket++;
+                r.stream = stream_ids[next];
+                r.count = counts[next];
+                r.dtype = dtypes[next];
+                r.t_submit = t;
+                S.per_stream[r.stream].push_back(r.ticket);
+                S.pending.push_back(r.ticket);
+                tickets[(size_t)next] = r.ticket;
+                S.reqs.emplace(r.ticket, r);
+                ++S.queued;
+                open.push_back(next++);
+                queued_any = true;
+            }
+            if (queued_any) S.cv_work.notify_one();
+            // collect what finished; its pool bytes go back at once
+            size_t w = 0;
+            for (size_t k = 0; k < open.size(); ++k) {
+                const int i = open[k];
+                auto it = S.reqs.find(tickets[(size_t)i]);
+                if (it == S.reqs.end()) return fail(MTGP_EDEVICE, "replayed request vanished");
+                Req &r = it->second;
+                if (r.state == R_DONE) {
+                    h_latency_ns[i] = r.t_done - (start + t_arrival_ns[i]);
+                    if (h_stages_ns) {
+                        h_stages_ns[3 * (size_t)i + 0] = r.t_admit - r.t_submit;
+                        h_stages_ns[3 * (size_t)i + 1] = r.t_launch - r.t_admit;
+                        h_stages_ns[3 * (size_t)i + 2] = r.t_done - r.t_launch;
+                    }
+                    if (r.bytes) S.pool->release(r.off, r.bytes);
+                    S.reqs.erase(it);
+                    ++finished;
+                    S.cv_work.notify_one();
+                } else if (r.state == R_FAILED || r.state == R_CANCELED) {
+                    return fail(MTGP_EDEVICE, "replayed request %d failed", i);
+                } else {
+                    open[w++] = i;
+                }
+            }
+            open.resize(w);
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(10));
+    }
+    return MTGP_OK;
+}
+
 int mtgp_wait(mtgp_server *srv, uint64_t ticket, uint64_t timeout_ns) {
     if (!srv) return fail(MTGP_EINVAL, "NULL server");
     Server &S = srv->s;

@@ -100,6 +100,7 @@ _SIGS = {
                            ctypes.c_int),
     "mtgp_submit": ([_VP, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _U64P], ctypes.c_int),
     "mtgp_submit_many": ([_VP, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
+    "mtgp_server_replay": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP], ctypes.c_int),
     "mtgp_poll": ([_VP, ctypes.c_uint64, _INTP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "mtgp_wait": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "mtgp_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
@@ -432,6 +433,21 @@ class Server:
         _check(lib().mtgp_submit_many(self.h, st.ctypes.data, ct.ctypes.data, dt.ctypes.data,
                                       int(st.shape[0]), tk.ctypes.data), "mtgp_submit_many")
         return tk
+
+    def replay(self, t_arrival_ns, stream_ids, counts, dtypes):
+        """Replays a request trace (native submission at the arrival times);
+        returns (latency ns (n,), stages ns (n, 3): queued, admitted, running)."""
+        ta = np.ascontiguousarray(t_arrival_ns, dtype=np.uint64)
+        st = np.ascontiguousarray(stream_ids, dtype=np.int32)
+        ct = np.ascontiguousarray(counts, dtype=np.uint64)
+        dt = np.ascontiguousarray(dtypes, dtype=np.int32)
+        n = int(ta.shape[0])
+        lat = np.zeros(n, dtype=np.uint64)
+        stg = np.zeros((n, 3), dtype=np.uint64)
+        _check(lib().mtgp_server_replay(self.h, ta.ctypes.data, st.ctypes.data, ct.ctypes.data,
+                                        dt.ctypes.data, n, lat.ctypes.data, stg.ctypes.data),
+               "mtgp_server_replay")
+        return lat, stg
 
     def poll(self, ticket: int):
         st = ctypes.c_int()
