@@ -33,20 +33,69 @@ static inline bool bit(const Poly &a, int i) {
     return w < a.size() && ((a[w] >> (i & 63)) & 1u);
 }
 
-Poly mul(const Poly &a, const Poly &b) {
-    if (a.empty() || b.empty()) return {};
-    Poly r(a.size() + b.size(), 0);
-    for (size_t i = 0; i < a.size(); ++i) {
+// r[0 .. 2n) ^= a[0 .. n) * b[0 .. n), schoolbook.
+static void mul_base(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
         if (!a[i]) continue;
-        for (size_t j = 0; j < b.size(); ++j) {
+        for (size_t j = 0; j < n; ++j) {
             uint64_t lo, hi;
             clmul(a[i], b[j], lo, hi);
             r[i + j] ^= lo;
             r[i + j + 1] ^= hi;
         }
     }
-    trim(r);
-    return r;
+}
+
+// r[0 .. 2n) = a * b for n-word operands (n = base * 2^k, base < 32),
+// Karatsuba: a = a0 + x^h a1, b likewise,
+// a b = a0 b0 + x^h ((a0 + a1)(b0 + b1) + a0 b0 + a1 b1) + x^2h a1 b1.
+// tmp holds 4n words of scratch.
+static void mul_kara(uint64_t *r, const uint64_t *a, const uint64_t *b, size_t n, uint64_t *tmp) {
+    if (n < 32) {
+        std::memset(r, 0, 2 * n * 8);
+        mul_base(r, a, b, n);
+        return;
+    }
+    const size_t h = n / 2;
+    uint64_t *sa = tmp, *sb = tmp + h, *mid = tmp + 2 * h, *rest = tmp + 4 * h;
+    mul_kara(r, a, b, h, rest);               // a0 b0 -> r[0, n)
+    mul_kara(r + n, a + h, b + h, h, rest);   // a1 b1 -> r[n, 2n)
+    for (size_t i = 0; i < h; ++i) {
+        sa[i] = a[i] ^ a[h + i];
+        sb[i] = b[i] ^ b[h + i];
+    }
+    mul_kara(mid, sa, sb, h, rest);           // (a0+a1)(b0+b1) -> mid[0, n)
+    for (size_t i = 0; i < n; ++i) mid[i] ^= r[i] ^ r[n + i];
+    for (size_t i = 0; i < n; ++i) r[h + i] ^= mid[i];
+}
+
+Poly mul(const Poly &a, const Poly &b) {
+    if (a.empty() || b.empty()) return {};
+    const size_t m = std::max(a.size(), b.size());
+    if (m < 32 || std::min(a.size(), b.size()) * 2 < m) {
+        Poly r(a.size() + b.size(), 0);
+        for (size_t i = 0; i < a.size(); ++i) {
+            if (!a[i]) continue;
+            for (size_t j = 0; j < b.size(); ++j) {
+                uint64_t lo, hi;
+                clmul(a[i], b[j], lo, hi);
+                r[i + j] ^= lo;
+                r[i + j + 1] ^= hi;
+            }
+        }
+        trim(r);
+        return r;
+    }
+    int k = 0;
+    while (((m + ((size_t)1 << k) - 1) >> k) >= 32) ++k;
+    const size_t n = ((m + ((size_t)1 << k) - 1) >> k) << k;  // base * 2^k >= m
+    std::vector<uint64_t> A(n, 0), B(n, 0), R(2 * n, 0), tmp(8 * n, 0);
+    std::memcpy(A.data(), a.data(), a.size() * 8);
+    std::memcpy(B.data(), b.data(), b.size() * 8);
+    mul_kara(R.data(), A.data(), B.data(), n, tmp.data());
+    R.resize(a.size() + b.size());
+    trim(R);
+    return R;
 }
 
 Poly square(const Poly &a) {

@@ -70,7 +70,7 @@ def _call(fn, *args, cap=4096):
     return from_words(o, n)
 
 
-@pytest.mark.parametrize("deg", [1, 5, 63, 64, 65, 200, 3217])
+@pytest.mark.parametrize("deg", [1, 5, 63, 64, 65, 200, 3217, 11213, 44497])
 def test_mulmod_and_powx(shim, deg):
     rng = np.random.default_rng(deg)
     p = (1 << deg) | int(rng.integers(0, 2**62)) | 1
