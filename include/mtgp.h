@@ -188,8 +188,9 @@ typedef struct mtgp_tuning {
     int jump_target_steps;  /* 0 = never split streams by jump-ahead; else the
                                least number of dependent steps per segment:
                                a batch splits the streams that need more
-                               steps than max(this, its total steps over
-                               0.8 x the streams the device runs at once) */
+                               steps than max(this, a multiple (0.75 to
+                               1.25) of its total steps over the streams
+                               the device runs at once) */
     int window_below_w;     /* with threads_per_stream = 64, streams with a
                                linear rec_tbl and step width W = N - pos below
                                this (at most 64) run the windowed scan instead

@@ -335,8 +335,12 @@ static uint64_t effective_target(const ParamSet &ps, const std::vector<Request> 
     const int wpb = t.threads_per_stream == 64 ? t.workgroup_size / 64 : 1;
     const int per_cu = variant_slots_per_cu(ps.N, t.threads_per_stream, t.outputs_per_lane, wpb);
     const uint64_t slots = (uint64_t)std::max(1, per_cu) * (uint64_t)std::max(1, device_cus());
-    // about 0.8 of the resident streams' worth of steps per segment
-    const uint64_t adaptive = total * 5 / (slots * 4);
+    // a multiple of the balanced share of steps per resident stream: more,
+    // shorter segments shorten the tail of the segment phase but every
+    // segment costs a jump (D N / 4 word operations); measured optimum about
+    // 0.75 at mexp 11213 and 1.25 at 23209 and 44497 (jumps 4-16x dearer)
+    const uint64_t share = total / slots;
+    const uint64_t adaptive = ps.N <= 400 ? share * 3 / 4 : share * 5 / 4;
     return std::max<uint64_t>((uint64_t)t.jump_target_steps, adaptive);
 }
 
