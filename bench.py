@@ -521,6 +521,20 @@ def run_paper(args):
         seed_invariant = None
     keys = {co[k].tobytes() for k in range(n) if deg[k] > 0}
     n_sets = cfg["param_sets"] if name == "P2" else n
+    # on-device screens of the last generated batch: gap test on [0, 2^30)
+    # (p = 1/4, 16 bins) and the Hamming-weight dependency table, chi-square
+    # p-values per stream (informative)
+    log("screens ...")
+    bins = 16
+    d_counts = torch.empty(n * (bins + 9), dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mtgp.screen(out, n, count, 0, 1 << 30, bins, d_counts)
+    torch.cuda.synchronize()
+    t_screen = time.perf_counter() - t0
+    screen = _screen_summary(d_counts.cpu().numpy().view(np.uint64).reshape(n, bins + 9), bins,
+                             0, 1 << 30)
+    screen["seconds"] = round(t_screen, 4)
     fill = _fill_gbps(torch, mtgp, out, stream)
     alg = n * count * 4 + n * (8 * N + 256)
     cpu = None
@@ -546,7 +560,33 @@ def run_paper(args):
                                     "full_degree": int((deg == mexp).sum()),
                                     "distinct": len(keys),
                                     "parameter_sets": n_sets,
-                                    "sets_with_seed_invariant_polynomial": seed_invariant}})
+                                    "sets_with_seed_invariant_polynomial": seed_invariant},
+                    "screens": screen})
+
+
+def _screen_summary(counts, bins, lo, hi):
+    """Chi-square p-values of the per-stream screening counts: gap bins
+    against p (1-p)^r, the weight-class table against independence of the
+    known class probabilities."""
+    import numpy as np
+    from math import comb
+    from scipy.stats import chi2
+    p = (hi - lo) / 2.0 ** 32
+    r = np.arange(bins - 1)
+    pg = np.concatenate([p * (1 - p) ** r, [(1 - p) ** (bins - 1)]])
+    w = np.array([comb(32, k) for k in range(33)], dtype=np.float64) / 2.0 ** 32
+    pc = np.array([w[:15].sum(), w[15:18].sum(), w[18:].sum()])
+    ph = np.outer(pc, pc).ravel()
+    g = counts[:, :bins].astype(np.float64)
+    h = counts[:, bins:].astype(np.float64)
+    eg = g.sum(1, keepdims=True) * pg
+    eh = h.sum(1, keepdims=True) * ph
+    pv_g = chi2.sf(((g - eg) ** 2 / eg).sum(1), bins - 1)
+    pv_h = chi2.sf(((h - eh) ** 2 / eh).sum(1), 8)
+    return {"gap_interval": [lo, hi], "gap_bins": bins,
+            "gap_p_below_1e-3": int((pv_g < 1e-3).sum()),
+            "hwd_p_below_1e-3": int((pv_h < 1e-3).sum()),
+            "expected_below_1e-3_if_uniform": round(1e-3 * counts.shape[0], 1)}
 
 
 def run_device_api(args):

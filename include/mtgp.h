@@ -255,6 +255,23 @@ int mtgp_stream_polynomials(const void *d_params, int n_streams,
                             uint32_t *h_coeffs, int words_per_stream,
                             int *h_degrees, void *stream);
 
+/* Screening statistics of generated uint32 outputs (informative, not a
+ * quality certificate; the paper screens statuses with TestU01's gap and
+ * Hamming-weight tests, Sec. 4 and 5).  For stream k, the count_per_stream
+ * words at d_outputs + k * count_per_stream:
+ *   gap test (Knuth, Sec. 3.3.2 D, gaps between consecutive hits): a hit is
+ *     a word in [gap_lo, gap_hi); the gap between consecutive hits j < j' is
+ *     j' - j - 1, counted in bin min(gap, gap_bins - 1);
+ *   Hamming-weight dependency: the weight class (popcount <= 14, 15..17,
+ *     >= 18) of each word and of the next one, counted in a 3x3 table.
+ * d_counts[k * (gap_bins + 9) ..] = the gap_bins gap counts, then the table
+ * row-major (device memory the caller owns; overwritten).  2 <= gap_bins
+ * <= 64, gap_lo < gap_hi, 2 <= count_per_stream < 2^32.  MTGP_EINVAL on a
+ * bad argument. */
+int mtgp_screen(const uint32_t *d_outputs, int n_streams,
+                uint64_t count_per_stream, uint32_t gap_lo, uint32_t gap_hi,
+                int gap_bins, uint64_t *d_counts, void *stream);
+
 /* Store-only fill of n words (bandwidth reference for the roofline). */
 int mtgp_fill_u32(uint32_t *d_out, uint64_t n_words, uint32_t value,
                   void *stream);

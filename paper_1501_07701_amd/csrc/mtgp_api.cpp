@@ -463,6 +463,21 @@ int mtgp_generate_workgroup(const void *d_params, uint32_t *d_states, int state_
     return e == hipSuccess ? MTGP_OK : hip_fail(e, "workgroup kernel");
 }
 
+int mtgp_screen(const uint32_t *d_outputs, int n_streams, uint64_t count_per_stream,
+                uint32_t gap_lo, uint32_t gap_hi, int gap_bins, uint64_t *d_counts,
+                void *stream) {
+    if (!d_outputs || !d_counts) return fail(MTGP_EINVAL, "NULL outputs or counts");
+    if (n_streams <= 0) return fail(MTGP_EINVAL, "n_streams=%d", n_streams);
+    if (count_per_stream < 2 || count_per_stream >= (1ull << 32))
+        return fail(MTGP_EINVAL, "count_per_stream %llu outside [2, 2^32)",
+                    (unsigned long long)count_per_stream);
+    if (gap_lo >= gap_hi) return fail(MTGP_EINVAL, "empty gap interval [%u, %u)", gap_lo, gap_hi);
+    if (gap_bins < 2 || gap_bins > 64) return fail(MTGP_EINVAL, "gap_bins %d outside [2, 64]", gap_bins);
+    hipError_t e = launch_screen(d_outputs, (uint32_t)n_streams, count_per_stream, gap_lo, gap_hi,
+                                 (uint32_t)gap_bins, d_counts, (hipStream_t)stream);
+    return e == hipSuccess ? MTGP_OK : hip_fail(e, "screen kernel");
+}
+
 int mtgp_fill_u32(uint32_t *d_out, uint64_t n_words, uint32_t value, void *stream) {
     if (!d_out || ((uintptr_t)d_out & 15u)) return fail(MTGP_EINVAL, "d_out must be 16-byte aligned");
     if (n_words == 0) return MTGP_OK;

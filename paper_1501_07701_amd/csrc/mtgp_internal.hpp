@@ -107,6 +107,8 @@ hipError_t launch_reset(uint32_t *counter, hipStream_t s);
 hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t stride,
                             uint32_t n_streams, uint64_t count, uint32_t *out, uint32_t f32,
                             uint32_t threads, uint32_t n_words, hipStream_t s);
+hipError_t launch_screen(const uint32_t *out, uint32_t n_streams, uint64_t count, uint32_t lo,
+                         uint32_t hi, uint32_t bins, uint64_t *counts, hipStream_t s);
 hipError_t launch_fill(uint32_t *out, uint64_t n_words, uint32_t value, int num_cus,
                        hipStream_t s);
 

@@ -901,6 +901,78 @@ hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t s
     return hipGetLastError();
 }
 
+// Screening statistics over generated uint32 outputs, one workgroup per
+// stream of `count` words at out + k*count (each thread scans a contiguous
+// chunk):
+//  gap test (Knuth, Sec. 3.3.2 D, between consecutive hits): a hit is a word
+//    in [lo, hi); the gap between consecutive hits j < j' is j' - j - 1,
+//    counted in bin min(gap, bins-1);
+//  Hamming-weight dependency: the weight class of a word (popcount <= 14,
+//    15..17, >= 18) and of its successor, counted in a 3x3 table.
+// counts[k * (bins + 9) ..] = gap bins, then the table row-major.
+constexpr int SCREEN_THREADS = 256;
+
+__device__ __forceinline__ uint32_t weight_class(uint32_t v) {
+    const uint32_t w = (uint32_t)__builtin_popcount(v);
+    return w <= 14u ? 0u : (w <= 17u ? 1u : 2u);
+}
+
+__global__ void __launch_bounds__(SCREEN_THREADS)
+screen_kernel(const uint32_t *__restrict__ out, uint64_t count, uint32_t lo, uint32_t hi,
+              uint32_t bins, uint64_t *__restrict__ counts) {
+    __shared__ uint32_t hist[64 + 9];
+    __shared__ int64_t first[SCREEN_THREADS], last[SCREEN_THREADS];
+    const uint32_t k = blockIdx.x, tid = threadIdx.x;
+    for (uint32_t i = tid; i < bins + 9; i += SCREEN_THREADS) hist[i] = 0;
+    __syncthreads();
+    gptr<const uint32_t> x = (gptr<const uint32_t>)(out + (uint64_t)k * count);
+    const uint64_t cs = (count + SCREEN_THREADS - 1) / SCREEN_THREADS;
+    const uint64_t b0 = (uint64_t)tid * cs < count ? (uint64_t)tid * cs : count;
+    const uint64_t b1 = b0 + cs < count ? b0 + cs : count;
+    int64_t f = -1, prev = -1;
+    uint32_t cur = b0 < b1 ? x[b0] : 0u;
+    for (uint64_t j = b0; j < b1; ++j) {
+        const uint32_t nxt = j + 1 < count ? x[j + 1] : 0u;
+        if (lo <= cur && cur < hi) {
+            if (prev >= 0) {
+                const uint64_t gap = j - (uint64_t)prev - 1;
+                atomicAdd(&hist[gap < bins - 1 ? gap : bins - 1], 1u);
+            } else {
+                f = (int64_t)j;
+            }
+            prev = (int64_t)j;
+        }
+        if (j + 1 < count) atomicAdd(&hist[bins + 3 * weight_class(cur) + weight_class(nxt)], 1u);
+        cur = nxt;
+    }
+    first[tid] = f;
+    last[tid] = prev;
+    __syncthreads();
+    if (tid == 0) {
+        // gaps that span chunk boundaries, in chunk order
+        int64_t pl = -1;
+        for (int t = 0; t < SCREEN_THREADS; ++t) {
+            if (first[t] < 0) continue;
+            if (pl >= 0) {
+                const uint64_t gap = (uint64_t)(first[t] - pl - 1);
+                hist[gap < bins - 1 ? gap : bins - 1] += 1u;
+            }
+            pl = last[t];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < bins + 9; i += SCREEN_THREADS)
+        counts[(uint64_t)k * (bins + 9) + i] = hist[i];
+}
+
+hipError_t launch_screen(const uint32_t *out, uint32_t n_streams, uint64_t count, uint32_t lo,
+                         uint32_t hi, uint32_t bins, uint64_t *counts, hipStream_t s) {
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(screen_kernel, dim3(n_streams), dim3(SCREEN_THREADS), 0, s, out, count,
+                       lo, hi, bins, counts);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(uint32_t *out, uint64_t n_words, uint32_t value, int num_cus,
                        hipStream_t s) {
     const uint64_t n_vec = n_words / 4;

@@ -94,6 +94,8 @@ _SIGS = {
                                  ctypes.c_int, ctypes.c_int, _VP, _VP], ctypes.c_int),
     "mtgp_stream_polynomials": ([_VP, ctypes.c_int, _VP, ctypes.c_int, _VP, _VP],
                                 ctypes.c_int),
+    "mtgp_screen": ([_VP, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                     ctypes.c_int, _VP, _VP], ctypes.c_int),
     "mtgp_fill_u32": ([_VP, ctypes.c_uint64, ctypes.c_uint32, _VP], ctypes.c_int),
     "mtgp_server_create": ([_VP, _VP, ctypes.c_int, ctypes.c_int, _VP, ctypes.c_uint64,
                             ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)],
@@ -329,6 +331,14 @@ def stream_polynomials(d_params, n_streams: int, mexp: int, stream=None):
                                          degrees.ctypes.data, _stream(stream)),
            "mtgp_stream_polynomials")
     return degrees, coeffs
+
+
+def screen(d_outputs, n_streams: int, count: int, gap_lo: int, gap_hi: int, gap_bins: int,
+           d_counts, stream=None) -> None:
+    """Gap-test and Hamming-weight-dependency counts per stream into
+    d_counts (n_streams x (gap_bins + 9) uint64 on the device)."""
+    _check(lib().mtgp_screen(_ptr(d_outputs), n_streams, count, gap_lo, gap_hi, gap_bins,
+                             _ptr(d_counts), _stream(stream)), "mtgp_screen")
 
 
 def fill_u32(d_out, n_words: int, value: int, stream=None) -> None:
