@@ -545,7 +545,7 @@ def run_paper(args):
         cpu = {"value": round(cv, 4), "unit": "G uint32/s", "cores": th, "kind": "oracle",
                "sample": "all %d streams x 2^16 uint32 outputs from the seeded states, "
                          "%.2f s wall on %d threads" % (n, dt, th)}
-    return _common(args, n * count / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
+    line = _common(args, n * count / (ms_step * 1e-3) / 1e9, "G uint32/s", ms_step,
                    {"workload": cfg["name"], "mexp": mexp, "streams": n,
                     "outputs_per_stream": count, "passes": ["u32"]},
                    alg / (ms_launch * 1e-3) / 1e9, cpu,
@@ -562,6 +562,11 @@ def run_paper(args):
                                     "parameter_sets": n_sets,
                                     "sets_with_seed_invariant_polynomial": seed_invariant},
                     "screens": screen})
+    line["data"] = ("synthetic: seeded random MTGP32 parameter sets of mexp 3217 (the Dynamic "
+                    "Creator's are not available), " +
+                    ("seed status 0 for every stream" if name == "P1"
+                     else "100 sets x 100 seeds drawn from splitmix64"))
+    return line
 
 
 def _screen_summary(counts, bins, lo, hi):
