@@ -38,6 +38,13 @@ namespace mtgp {
 template <typename T>
 using gptr = __attribute__((address_space(1))) T *;
 
+// a ^ b ^ c in one VALU operation (v_bitop3_b32 with truth table 0x96, the
+// odd-parity function of its three inputs); hipcc keeps XOR chains as
+// two-input operations.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 template <int TPS>
 __device__ __forceinline__ void group_sync() {
     if constexpr (TPS == 64) {
@@ -167,9 +174,8 @@ struct Core {
         while (done < count) {
             const uint64_t rem = count - done;
             const uint32_t S = rem < W ? (uint32_t)rem : W;
-            uint32_t X = (a & p.mask) ^ b;
-            X ^= X << p.sh1;
-            const uint32_t x = rec<LIN>(p, tbl, X ^ (c >> p.sh2));
+            const uint32_t X = (a & p.mask) ^ b;
+            const uint32_t x = rec<LIN>(p, tbl, xor3(X, X << p.sh1, c >> p.sh2));
             // lanes >= S write into the next step's slots, which it rewrites
             buf[h + lane] = x;
             const uint32_t hh_cur = hh;
@@ -192,9 +198,10 @@ struct Core {
 
     // y = P v for a 32x32 GF(2) matrix given as 8 nibble tables of 16 words.
     static __device__ __forceinline__ uint32_t mat_apply(const uint32_t *t, uint32_t v) {
-        uint32_t y = 0;
+        uint32_t y = t[(v & 15u)] ^ t[16 + ((v >> 4) & 15u)];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) y ^= t[k * 16 + ((v >> (4 * k)) & 15u)];
+        for (int k = 2; k < 8; k += 2)
+            y = xor3(y, t[k * 16 + ((v >> (4 * k)) & 15u)], t[k * 16 + 16 + ((v >> (4 * k + 4)) & 15u)]);
         return y;
     }
 
@@ -334,9 +341,8 @@ struct Core {
         uint32_t x[KE], r[KE];
 #pragma unroll
         for (int k = 0; k < KE; ++k) {
-            uint32_t X = (a[k] & p.mask) ^ b[k];
-            X ^= X << p.sh1;
-            x[k] = rec<false>(p, tbl, X ^ (c[k] >> p.sh2));
+            const uint32_t X = (a[k] & p.mask) ^ b[k];
+            x[k] = rec<false>(p, tbl, xor3(X, X << p.sh1, c[k] >> p.sh2));
             r[k] = temper<F32>(tbl, x[k], hh[k]);
         }
         uint32_t *w = buf + (h + lane);
@@ -580,6 +586,7 @@ constexpr int JUMP_PL = JUMP_CH + JUMP_MT;  // plane length (words)
 constexpr int JUMP_LDS_BYTES = 16 * JUMP_PL * 4;
 
 typedef uint32_t jv4 __attribute__((ext_vector_type(4)));
+
 template <int JA>
 __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uint32_t> g,
                                           uint32_t *__restrict__ out, bool active, uint32_t D,
@@ -617,13 +624,20 @@ __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uin
                 uint32_t bits = __builtin_amdgcn_readlane(gv, cw);
                 if (cw == nw - 1 && (ch & 31)) bits &= (1u << (ch & 31)) - 1u;
                 const uint32_t *col = planes + 32 * cw + 4 * lane;
+                // two nibbles per three-input XOR
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t v = (bits >> (4 * k)) & 15u;
-                    const uint32_t *src = col + v * JUMP_PL + 4 * k;
+                for (int k = 0; k < 8; k += 2) {
+                    const uint32_t v0 = (bits >> (4 * k)) & 15u;
+                    const uint32_t v1 = (bits >> (4 * k + 4)) & 15u;
+                    const uint32_t *s0 = col + v0 * JUMP_PL + 4 * k;
+                    const uint32_t *s1 = col + v1 * JUMP_PL + 4 * k + 4;
 #pragma unroll
-                    for (int j = 0; j < JA; ++j)
-                        acc[j] ^= *reinterpret_cast<const jv4 *>(src + 256 * j);
+                    for (int j = 0; j < JA; ++j) {
+                        const jv4 a = *reinterpret_cast<const jv4 *>(s0 + 256 * j);
+                        const jv4 b = *reinterpret_cast<const jv4 *>(s1 + 256 * j);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) acc[j][e] = xor3(acc[j][e], a[e], b[e]);
+                    }
                 }
             }
         }
