@@ -48,6 +48,16 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(params, seeds, count, threads):
     """The CPU oracle, as it stands, on a bounded sample of the workload:
     every stream, `count` uint32 outputs then `count` float32 outputs from
@@ -163,14 +173,18 @@ def run_c2(args):
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(16, len(os.sched_getaffinity(0)))
-        sample_count = 1 << 23
         log("cpu baseline: oracle on %d threads ..." % threads)
-        cv, dt = cpu_baseline(params, seeds, sample_count, threads)
+        cv, dt = cpu_baseline(params, seeds, count, threads)
+        log("cpu baseline: oracle on 1 thread ...")
+        cv1, dt1 = cpu_baseline(params[:8], seeds[:8], 1 << 22, 1)
         cpu = {"value": round(cv, 4), "unit": "G uint32/s", "cores": threads,
                "kind": "oracle",
-               "sample": "all 128 streams x 2^23 outputs (half the workload's "
-                         "length), uint32 pass then float32 pass from the seeded "
-                         "states, %.2f s wall on %d threads" % (dt, threads)}
+               "sample": "the whole workload: all 128 streams x 2^24 outputs, "
+                         "uint32 pass then float32 pass from the seeded states, "
+                         "%.2f s wall on %d threads" % (dt, threads),
+               "value_1_thread": round(cv1, 4),
+               "sample_1_thread": "8 streams x 2^22 outputs, both passes, %.2f s" % dt1,
+               "cpu_model": cpu_model()}
 
     line = {
         "metric": "G uint32/s and % HBM write roofline",
