@@ -78,15 +78,31 @@ __device__ inline void mtgp_device_begin(mtgp_device_stream &s, const uint32_t *
     __syncthreads();
 }
 
+/* Orders the LDS accesses of one wave across a step without a workgroup
+ * barrier (a wave's LDS operations complete in issue order). */
+__device__ inline void mtgp_device_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 /* Next n (<= blockDim.x) outputs: thread t < n receives output t as raw
- * bits (uint32 output, or the float32 output's bit pattern when F32). */
+ * bits (uint32 output, or the float32 output's bit pattern when F32).
+ * The new state words are produced first, in steps of at most W words (a
+ * word's recursion reads words at least W older); streams with W < 64 take
+ * their steps on the first wave alone, which needs no workgroup barrier
+ * between steps and carries each lane's pos tap in a register (the word a
+ * lane makes is its own tap W words later).  Every thread then tempers its
+ * own word. */
 template <bool F32>
 __device__ inline uint32_t mtgp_device_draw_bits(mtgp_device_stream &s, uint32_t n) {
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     uint32_t *buf = s.buf;
     const uint32_t *tbl = s.buf + s.cap;
     if (s.h + T > s.cap) {
-        // cap >= 2N + T: the last N words never overlap the front
+        // every thread is done with the previous draw's words; cap >= 2N + T,
+        // so the last N words never overlap the front
+        __syncthreads();
         uint32_t v[4];
         for (uint32_t i0 = 0; i0 < s.N; i0 += 4 * T) {
             for (int j = 0; j < 4; ++j) {
@@ -101,28 +117,50 @@ __device__ inline uint32_t mtgp_device_draw_bits(mtgp_device_stream &s, uint32_t
         __syncthreads();
         s.h = s.N;
     }
-    uint32_t result = 0;
-    const uint32_t smax = s.W < T ? s.W : T;
-    for (uint32_t o = 0; o < n; o += smax) {
-        const uint32_t S = (n - o) < smax ? (n - o) : smax;
-        if (tid >= o && tid < o + S) {
-            const uint32_t k = s.h + (tid - o);  // buffer index of this word
-            uint32_t X = (buf[k - s.N] & s.mask) ^ buf[k - s.N + 1];
-            X ^= X << s.sh1;
-            const uint32_t Y = X ^ (buf[k - s.W] >> s.sh2);
-            const uint32_t x = Y ^ tbl[Y & 15u];
-            buf[k] = x;
-            uint32_t H = buf[k - s.W - 1];
-            H ^= H >> 16;
-            H ^= H >> 8;
-            if (F32)
-                result = __float_as_uint(__uint_as_float((x >> 9) ^ tbl[32 + (H & 15u)]) - 1.0f);
-            else
-                result = x ^ tbl[16 + (H & 15u)];
+    const uint32_t h0 = s.h;
+    if (s.W < 64u) {
+        if (tid < 64u) {
+            uint32_t c = tid < s.W ? buf[h0 - s.W + tid] : 0u;  // x_{k-W} of word k = h0 + tid
+            for (uint32_t o = 0; o < n; o += s.W) {
+                if (tid < s.W && o + tid < n) {
+                    const uint32_t k = h0 + o + tid;
+                    uint32_t X = (buf[k - s.N] & s.mask) ^ buf[k - s.N + 1];
+                    X ^= X << s.sh1;
+                    const uint32_t Y = X ^ (c >> s.sh2);
+                    c = Y ^ tbl[Y & 15u];
+                    buf[k] = c;
+                }
+                mtgp_device_wave_sync();
+            }
         }
-        __syncthreads();
-        s.h += S;
+    } else {
+        const uint32_t smax = s.W < T ? s.W : T;
+        for (uint32_t o = 0; o < n; o += smax) {
+            const uint32_t S = (n - o) < smax ? (n - o) : smax;
+            if (tid >= o && tid < o + S) {
+                const uint32_t k = h0 + tid;
+                uint32_t X = (buf[k - s.N] & s.mask) ^ buf[k - s.N + 1];
+                X ^= X << s.sh1;
+                const uint32_t Y = X ^ (buf[k - s.W] >> s.sh2);
+                buf[k] = Y ^ tbl[Y & 15u];
+            }
+            __syncthreads();
+        }
     }
+    __syncthreads();
+    uint32_t result = 0;
+    if (tid < n) {
+        const uint32_t k = h0 + tid;
+        const uint32_t x = buf[k];
+        uint32_t H = buf[k - s.W - 1];
+        H ^= H >> 16;
+        H ^= H >> 8;
+        if (F32)
+            result = __float_as_uint(__uint_as_float((x >> 9) ^ tbl[32 + (H & 15u)]) - 1.0f);
+        else
+            result = x ^ tbl[16 + (H & 15u)];
+    }
+    s.h = h0 + n;
     return result;
 }
 
