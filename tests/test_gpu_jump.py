@@ -57,7 +57,8 @@ def _params(mexp, master):
     return p
 
 
-@pytest.mark.parametrize("mexp,count", [(3217, 60000), (11213, 150000), (44497, 300000)])
+@pytest.mark.parametrize("mexp,count", [(3217, 60000), (11213, 150000), (23209, 200000),
+                                        (44497, 300000)])
 def test_split_batch_matches_oracle(torch, mexp, count):
     _say("case split mexp=%d count=%d" % (mexp, count))
     p = _params(mexp, 0x5EED + mexp)
