@@ -44,6 +44,7 @@ def _params(mexp, master):
     p[2, 1] = N - 33         # W = 33
     p[3, 3] = 0              # sh2 = 0
     p[4, 2] = 0              # sh1 = 0
+    p[5, 1] = N - 55         # W = 55: 2W >= N at mexp 3217 (no read-ahead)
     return p
 
 
