@@ -765,7 +765,7 @@ def main():
     if args.gpus != 1:
         print("bench.py measures one GPU: the streams are independent and a "
               "multi-GPU run would only shard them (no communication); "
-              "--gpus %d is not supported in this build" % args.gpus, file=sys.stderr)
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
