@@ -118,6 +118,16 @@ def run_c2(args):
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
+    # one untimed step with phase timestamps (a separate graph with stamp
+    # kernels between the phases): prefix, jump and segment durations
+    mtgp.set_phase_timing(True)
+    phases = {}
+    for name, items, ws in (("u32", items_u, ws_u), ("f32", items_f, ws_f)):
+        g.reseed()
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, items, ws)
+        phases[name] = [round(x, 1) for x in mtgp.batch_phase_times(ws)]
+    mtgp.set_phase_timing(False)
+    seg_us = float(np.mean([phases["u32"][2], phases["f32"][2]]))
     log("timing %d step(s) ..." % args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -213,6 +223,10 @@ def run_c2(args):
         "store_only_fill_GBps": round(fill_gbps, 1),
         "unsplit_critical_path_steps": crit_steps,
         "min_step_width": int(W.min()),
+        "phases_us": {"prefix_jumps_segments_u32": phases["u32"],
+                      "prefix_jumps_segments_f32": phases["f32"],
+                      "note": "one untimed call per pass with stamp kernels between phases"},
+        "segment_phase_GBps": round(n * count * 4 / (seg_us * 1e-6) / 1e9, 1),
         "jump_ahead": {"target_steps": tun.jump_target_steps,
                        "workspace_bytes": int(ws_u.numel()),
                        "plan_build_s": round(t_plan, 3),

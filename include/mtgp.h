@@ -173,6 +173,20 @@ int mtgp_generate_batch(const void *d_params, uint32_t *d_states,
                         int n_items, void *d_workspace, size_t workspace_bytes,
                         void *stream);
 
+/* Phase timing, for measurement.  While enabled (process-wide; default
+ * off), every mtgp_generate_batch call writes four device wall-clock
+ * timestamps into its workspace header: at its start, after the prefix
+ * items, after the jump-ahead evaluation and at its end.  Each costs a
+ * one-thread kernel launch between the phases, so leave it off for timed
+ * runs.  Always MTGP_OK. */
+int mtgp_set_phase_timing(int enable);
+
+/* Synchronises `stream` and returns in h_us[0..2] the prefix, jump and
+ * segment phase durations in microseconds of the last batch call on
+ * d_workspace that ran with phase timing enabled.  MTGP_EINVAL if the
+ * workspace holds no timestamps. */
+int mtgp_batch_phase_times(void *d_workspace, void *stream, double *h_us);
+
 /* Synchronises `stream`, returns in *n the number of jump-ahead segment
  * checks that failed in batches run on this workspace since the last call,
  * and resets the count. */

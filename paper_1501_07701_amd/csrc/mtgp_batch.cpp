@@ -458,12 +458,14 @@ struct GraphKey {
     uint32_t nA, nB, nC;
     const void *params;
     int N, tps, k, wg, win, device;
+    bool stamps;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, win, device) <
+        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, win, device, stamps) <
                std::tie(o.ws, o.nA, o.nB, o.nC, o.params, o.N, o.tps, o.k, o.wg, o.win,
-                        o.device);
+                        o.device, o.stamps);
     }
 };
+std::atomic<bool> g_stamps{false};  // phase timestamps in every batch call
 std::mutex g_graph_mu;
 std::map<GraphKey, hipGraphExec_t> g_graphs;
 std::map<int, hipStream_t> g_capture_streams;
@@ -477,8 +479,16 @@ bool graphs_enabled() {
 // Launches the three phases of a planned batch on `s`.
 static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, uint32_t nA,
                          uint32_t nB, uint32_t nC, const Layout &L, const mtgp_tuning &t,
-                         hipStream_t s) {
+                         hipStream_t s, bool stamps) {
     uint32_t *hdr = (uint32_t *)ws;
+    uint64_t *ts = (uint64_t *)(ws + HDR_STAMP_BYTE);
+    auto stamp = [&](int i) -> int {
+        if (!stamps) return MTGP_OK;
+        const hipError_t e = launch_stamp(ts + i, s);
+        return e == hipSuccess ? MTGP_OK : hip_fail(e, "stamp kernel");
+    };
+    int rc0 = stamp(0);
+    if (rc0) return rc0;
     LaunchArgs a{};
     a.params = (const uint32_t *)d_params;
     a.err = hdr + 2;
@@ -494,16 +504,20 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, uin
         int rc = launch_tuned(ps.N, t, a);
         if (rc) return rc;
     }
+    if ((rc0 = stamp(1))) return rc0;
     if (nB) {
         if ((e = launch_jump((const JumpItem *)(ws + L.off_B), nB, device_cus(), s)) !=
             hipSuccess)
             return hip_fail(e, "jump kernel");
     }
+    if ((rc0 = stamp(2))) return rc0;
     if ((e = launch_reset(hdr + 1, s)) != hipSuccess) return hip_fail(e, "reset kernel");
     a.items = (const BatchItem *)(ws + L.off_C);
     a.n_items = nC;
     a.counter = hdr + 1;
-    return launch_tuned(ps.N, t, a);
+    const int rc = launch_tuned(ps.N, t, a);
+    if (rc) return rc;
+    return stamp(3);
 }
 
 int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
@@ -688,13 +702,14 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         L.off_C = L.off_B + al256((size_t)nB * sizeof(JumpItem));
     }
 
+    const bool stamps = g_stamps.load();
     if (!use_graph || !graphs_enabled())
-        return launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, s);
+        return launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, s, stamps);
 
     int dev = 0;
     (void)hipGetDevice(&dev);
     GraphKey key{d_ws, nA, nB, nC, d_params, ps->N, t.threads_per_stream, t.outputs_per_lane,
-                 t.workgroup_size, t.window_below_w, dev};
+                 t.workgroup_size, t.window_below_w, dev, stamps};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -713,7 +728,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         }
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int rc = launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, cs);
+        int rc = launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, cs, stamps);
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(cs, &gr);
         if (rc) {
@@ -858,6 +873,29 @@ int mtgp_generate_batch(const void *d_params, uint32_t *d_states, int state_stri
                         size_t workspace_bytes, void *stream) {
     return batch_common(d_params, d_states, state_stride, h_items, n_items, d_workspace,
                         workspace_bytes, (hipStream_t)stream, nullptr, true, g_stage);
+}
+
+int mtgp_set_phase_timing(int enable) {
+    g_stamps.store(enable != 0);
+    return MTGP_OK;
+}
+
+int mtgp_batch_phase_times(void *d_workspace, void *stream, double *h_us) {
+    if (!d_workspace || !h_us) return fail(MTGP_EINVAL, "NULL workspace or h_us");
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t ts[4] = {0, 0, 0, 0};
+    hipError_t e = hipMemcpyAsync(ts, (char *)d_workspace + HDR_STAMP_BYTE, sizeof ts,
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "read phase timestamps");
+    if (!ts[0] || ts[1] < ts[0] || ts[2] < ts[1] || ts[3] < ts[2])
+        return fail(MTGP_EINVAL, "no phase timestamps in this workspace (timing disabled?)");
+    int dev = 0, khz = 0;
+    (void)hipGetDevice(&dev);
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || khz <= 0) return hip_fail(e, "wall clock rate");
+    for (int i = 0; i < 3; ++i) h_us[i] = (double)(ts[i + 1] - ts[i]) * 1e3 / (double)khz;
+    return MTGP_OK;
 }
 
 int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n) {

@@ -104,6 +104,11 @@ int variant_slots_per_cu(int n_words, int tps, int k, int wpb);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s);
 hipError_t launch_reset(uint32_t *counter, hipStream_t s);
+// Batch workspace header: claim counters (words 0, 1), segment-check errors
+// (word 2), phase timestamps (64-bit words from byte HDR_STAMP_BYTE: start,
+// after the prefix items, after the jumps, end).
+constexpr size_t HDR_STAMP_BYTE = 64;
+hipError_t launch_stamp(uint64_t *dst, hipStream_t s);
 hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t stride,
                             uint32_t n_streams, uint64_t count, uint32_t *out, uint32_t f32,
                             uint32_t threads, uint32_t n_words, hipStream_t s);

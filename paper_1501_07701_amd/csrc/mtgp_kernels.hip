@@ -704,6 +704,11 @@ __global__ void seed_kernel(const uint32_t *__restrict__ params,
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
 
+// Device timestamp (the constant-rate wall clock) for phase timing.
+__global__ void stamp_kernel(uint64_t *dst) {
+    if (threadIdx.x == 0) *dst = wall_clock64();
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // Store-only fill: the achievable write bandwidth next to the generator
@@ -866,6 +871,12 @@ hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride
 hipError_t launch_reset(uint32_t *counter, hipStream_t s) {
     (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(uint64_t *dst, hipStream_t s) {
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, s, dst);
     return hipGetLastError();
 }
 

@@ -108,6 +108,8 @@ _SIGS = {
     "mtgp_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
     "mtgp_request_times": ([_VP, ctypes.c_uint64, _U64P, _U64P, _U64P, _U64P], ctypes.c_int),
     "mtgp_server_destroy": ([_VP], ctypes.c_int),
+    "mtgp_set_phase_timing": ([ctypes.c_int], ctypes.c_int),
+    "mtgp_batch_phase_times": ([_VP, _VP, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "mtgp_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "mtgp_last_error_detail": ([], ctypes.c_char_p),
 }
@@ -256,6 +258,19 @@ def batch_errors(d_workspace, stream=None) -> int:
     _check(lib().mtgp_batch_errors(_ptr(d_workspace), _stream(stream), ctypes.byref(n)),
            "mtgp_batch_errors")
     return int(n.value)
+
+
+def set_phase_timing(enable: bool) -> None:
+    _check(lib().mtgp_set_phase_timing(1 if enable else 0), "mtgp_set_phase_timing")
+
+
+def batch_phase_times(d_workspace, stream=None):
+    """(prefix, jumps, segments) durations in microseconds of the last batch
+    call on the workspace that ran with phase timing enabled."""
+    us = (ctypes.c_double * 3)()
+    _check(lib().mtgp_batch_phase_times(_ptr(d_workspace), _stream(stream), us),
+           "mtgp_batch_phase_times")
+    return tuple(us)
 
 
 def get_tuning(mexp: int) -> Tuning:

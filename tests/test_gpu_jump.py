@@ -133,3 +133,37 @@ def test_split_after_reseed_and_graph_replays(torch):
                 assert np.array_equal(h[k], exp[k]), (rep, k)
         assert mtgp.batch_errors(ws) == 0
         g.close()
+
+
+def test_phase_timing_stamps(torch):
+    """Phase timestamps: present only while enabled, ordered, and the batch
+    results do not change with the stamp kernels in the graph."""
+    _say("case phase timing")
+    mexp, count = 11213, 150000
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 4, 0x7A)
+    seeds = np.arange(1, 5, dtype=np.uint32)
+    with _Tune(mexp, 256):
+        g = mtgp.Generators(p, seeds)
+        outs = [torch.empty(count, dtype=torch.int32, device="cuda") for _ in range(4)]
+        items = [(k, 0, count, outs[k]) for k in range(4)]
+        ws = g.workspace(items)
+        g.batch(items, ws)
+        with pytest.raises(mtgp.MTGPError):
+            mtgp.batch_phase_times(ws)                 # never stamped
+        first = [_host(o).copy() for o in outs]
+        mtgp.set_phase_timing(True)
+        try:
+            g.reseed()
+            g.batch(items, ws)
+            us = mtgp.batch_phase_times(ws)
+        finally:
+            mtgp.set_phase_timing(False)
+        assert all(x >= 0 for x in us) and us[1] > 0 and us[2] > 0, us
+        assert mtgp.batch_errors(ws) == 0
+        states = np.stack([oracle.seed(int(s), N) for s in seeds])
+        for k in range(4):
+            o, _ = oracle.generate(p[k], states[k], count, False)
+            assert np.array_equal(_host(outs[k]), np.asarray(o).view(np.uint32)), k
+            assert np.array_equal(first[k], _host(outs[k])), k
+        g.close()
