@@ -277,6 +277,20 @@ def _timed_steps(torch, step, warmup, steps):
     return ms_per_step, sum(launch) / len(launch)
 
 
+def _phases(g, mtgp, arr, ws, out_bytes):
+    """One untimed call with phase timestamps: (prefix, jumps, segments) in
+    microseconds and the segment phase's output rate in GB/s."""
+    mtgp.set_phase_timing(True)
+    try:
+        g.reseed()
+        mtgp.generate_batch(g.d_params, g.d_states, g.stride, arr, ws)
+        us = [round(x, 1) for x in mtgp.batch_phase_times(ws)]
+    finally:
+        mtgp.set_phase_timing(False)
+    return {"phases_us_prefix_jumps_segments": us,
+            "segment_phase_GBps": round(out_bytes / (us[2] * 1e-6) / 1e9, 1) if us[2] else None}
+
+
 def _pair(torch, stream):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -358,6 +372,7 @@ def run_c3(args):
     if mtgp.batch_errors(ws):
         log("jump-ahead segment checks failed")
         sys.exit(3)
+    phases = _phases(g, mtgp, arr, ws, n * count * 4)
     fill = _fill_gbps(torch, mtgp, out, stream)
     alg = n * count * 4 + n * (8 * N + 256)
     cpu = None
@@ -376,6 +391,7 @@ def run_c3(args):
                    alg / (ms_launch * 1e-3) / 1e9, cpu,
                    {"avg_generate_launch_ms": round(ms_launch, 3),
                     "store_only_fill_GBps": round(fill, 1),
+                    **phases,
                     "autotuned": {"threads_per_stream": best.threads_per_stream,
                                   "outputs_per_lane": best.outputs_per_lane,
                                   "workgroup_size": best.workgroup_size,
@@ -433,6 +449,7 @@ def run_c4(args):
     if mtgp.batch_errors(ws):
         log("jump-ahead segment checks failed")
         sys.exit(3)
+    phases = _phases(g, mtgp, arr, ws, total * 4)
 
     # one launch per stream, in order
     def per_stream(split):
@@ -483,6 +500,7 @@ def run_c4(args):
                    alg / (ms_launch * 1e-3) / 1e9, cpu,
                    {"avg_generate_launch_ms": round(ms_launch, 3),
                     "store_only_fill_GBps": round(fill, 1),
+                    **phases,
                     "autotuned": dict(zip(("threads_per_stream", "outputs_per_lane",
                                            "workgroup_size", "jump_target_steps",
                                            "window_below_w"), best.as_tuple()),
@@ -531,6 +549,7 @@ def run_paper(args):
     if mtgp.batch_errors(ws):
         log("jump-ahead segment checks failed")
         sys.exit(3)
+    phases = _phases(g, mtgp, arr, ws, n * count * 4)
     log("stream polynomials ...")
     t0 = time.perf_counter()
     deg, co = mtgp.stream_polynomials(g.d_params, n, mexp)
@@ -579,6 +598,7 @@ def run_paper(args):
                    alg / (ms_launch * 1e-3) / 1e9, cpu,
                    {"avg_generate_launch_ms": round(ms_launch, 3),
                     "store_only_fill_GBps": round(fill, 1),
+                    **phases,
                     "plan_build_s": round(t_plan, 2),
                     "polynomials": {"seconds": round(t_poly, 2),
                                     "unverified": int((deg < 0).sum()),
