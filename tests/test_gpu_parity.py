@@ -356,3 +356,66 @@ def test_c4_full_size_sampled(torch):
         assert np.array_equal(st[k], s_end), k
     del out
     g.close()
+
+
+def test_zero_counts_leave_streams_untouched(torch):
+    """count = 0 is a valid no-op for the plain, workgroup and batch entry
+    points: states do not move and the next call continues from the seed."""
+    _say("case zero counts")
+    mexp = 11213
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 3, 0x2E0)
+    seeds = np.array([5, 6, 7], dtype=np.uint32)
+    g = mtgp.Generators(p, seeds)
+    before = g.states_host().copy()
+    dummy = torch.empty(1, dtype=torch.int32, device="cuda")
+    mtgp.generate(g.d_params, g.d_states, g.stride, 3, 0, dummy, mtgp.U32)
+    mtgp.generate_workgroup(g.d_params, g.d_states, g.stride, 3, 0, dummy, mtgp.F32, 256)
+    ws = g.workspace(3)
+    g.batch([(k, 0, 0, dummy) for k in range(3)], ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.states_host(), before)
+    out = g.generate(100)
+    for k in range(3):
+        exp, _ = oracle.generate(p[k], oracle.seed(int(seeds[k]), N), 100, False)
+        assert np.array_equal(_host(out).reshape(3, 100)[k], np.asarray(exp).view(np.uint32)), k
+    g.close()
+
+
+def test_single_stream_beyond_2p32_outputs(torch):
+    """One stream of 2^32 + 1000 outputs in one batch call (jump-ahead
+    splits it): 64-bit output indexing past 2^32 words.  The oracle runs the
+    whole stream in chunks and keeps the head, the words around 2^32 and the
+    final state."""
+    _say("case one stream beyond 2^32")
+    mexp = 11213
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 1, 0x2F32)
+    seeds = np.array([11], dtype=np.uint32)
+    count = (1 << 32) + 1000
+    g = mtgp.Generators(p, seeds)
+    out = torch.empty(count, dtype=torch.int32, device="cuda")
+    items = [(0, mtgp.U32, count, out)]
+    ws = g.workspace(items)
+    g.batch(items, ws)
+    assert mtgp.batch_errors(ws) == 0
+    head = _host(out[:1000])
+    tail = _host(out[(1 << 32) - 1000:])
+    state = oracle.seed(int(seeds[0]), N)
+    exp_head, exp_tail = None, []
+    chunk, done = 1 << 25, 0
+    while done < count:
+        c = min(chunk, count - done)
+        o, state = oracle.generate(p[0], state, c, False)
+        o = np.asarray(o).view(np.uint32)
+        if done == 0:
+            exp_head = o[:1000].copy()
+        lo = max(done, (1 << 32) - 1000)
+        if lo < done + c:
+            exp_tail.append(o[lo - done:].copy())
+        done += c
+    assert np.array_equal(head, exp_head)
+    assert np.array_equal(tail, np.concatenate(exp_tail))
+    assert np.array_equal(g.states_host()[0], state)
+    del out
+    g.close()
