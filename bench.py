@@ -705,7 +705,7 @@ def run_c5(args):
     t0 = time.perf_counter()
     mtgp.stream_polynomials(g.d_params, n_streams, mexp)
     t_warm = time.perf_counter() - t0
-    srv = mtgp.Server(g, cfg["pool_bytes"], inflight=args.inflight, max_batch_items=512,
+    srv = mtgp.Server(g, cfg["pool_bytes"], inflight=args.inflight, max_batch_items=128,
                       batch_window_ns=int(args.batch_window_us * 1000),
                       workspace_bytes_per_batch=128 << 20)
     try:

@@ -265,6 +265,13 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
     return MTGP_OK;
 }
 
+// True when the stream's cached powers already serve segment length lseg
+// up to cmax.
+static bool g_ready(StreamJump &sj, uint64_t lseg, int cmax) {
+    std::lock_guard<std::mutex> lk(sj.mu);
+    return sj.lseg == lseg && (int)sj.g.size() >= cmax - 1;
+}
+
 // g[c-1] = x^(c*lseg-1) mod p for c = 1 .. cmax-1.
 static void ensure_g(StreamJump &sj, uint64_t lseg, int cmax) {
     std::lock_guard<std::mutex> lk(sj.mu);
@@ -408,7 +415,10 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_
     return L;
 }
 
-static int upload(Staging &st, const uint8_t *src, size_t n, void *d_dst, hipStream_t s) {
+// Pinned staging for the uploaded plan: acquire waits until the previous
+// upload from this buffer has been consumed, then hands out at least n
+// bytes; the plan is written in place and commit copies it to the device.
+static int stage_acquire(Staging &st, size_t n, uint8_t **out) {
     if (st.pending) {
         hipError_t e = hipEventSynchronize(st.done);
         if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
@@ -429,8 +439,12 @@ static int upload(Staging &st, const uint8_t *src, size_t n, void *d_dst, hipStr
         hipError_t e = hipEventCreateWithFlags(&st.done, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
+    *out = st.host;
+    return MTGP_OK;
+}
+
+static int stage_commit(Staging &st, size_t n, void *d_dst, hipStream_t s) {
     if (n == 0) return MTGP_OK;
-    std::memcpy(st.host, src, n);
     hipError_t e = hipMemcpyAsync(d_dst, st.host, n, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(work list)");
     e = hipEventRecord(st.done, s);
@@ -586,19 +600,25 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         if (L.total > ws_bytes)
             return fail(MTGP_EINVAL, "workspace of %zu bytes too small (need %zu)", ws_bytes,
                         L.total);
-        // polynomials
+        // polynomials: only streams whose cache lacks them (a thread per
+        // stream costs more than a batch of cached lookups)
         std::vector<Seg *> split;
         for (Seg &g : segs)
-            if (g.C > 1) split.push_back(&g);
+            if (g.C > 1 && !g_ready(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1)))
+                split.push_back(&g);
         parallel_for((int)split.size(), [&](int i) {
             const Seg &g = *split[i];
             ensure_g(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1));
         });
 
-        // build the uploaded image [0, up_end): a zeroed header (claim
-        // counters, error count), the item tables, countdowns, polynomials
-        std::vector<uint8_t> img(L.up_end, 0);
-        auto at = [&](size_t off) { return img.data() + off; };
+        // build the uploaded image [0, up_end) in the pinned staging buffer:
+        // a zeroed header (claim counters, error count, stamps), the item
+        // tables, countdowns, polynomials (every byte that is read is
+        // written; the alignment gaps between tables are never read)
+        uint8_t *img = nullptr;
+        if (int rc = stage_acquire(stage, L.up_end, &img)) return rc;
+        std::memset(img, 0, 256);
+        auto at = [&](size_t off) { return img + off; };
         std::vector<std::pair<uint64_t, BatchItem>> A, C;
         std::vector<JumpItem> B;
         size_t raw_off = L.off_raw, js_off = L.off_js, poly_off = L.off_poly;
@@ -690,7 +710,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         nA = (uint32_t)A.size();
         nB = (uint32_t)B.size();
         nC = (uint32_t)C.size();
-        int rc = upload(stage, img.data(), img.size(), ws, s);
+        int rc = stage_commit(stage, L.up_end, ws, s);
         if (rc) return rc;
         std::lock_guard<std::mutex> lk(g_ws_mu);
         g_ws[d_ws] = WsRecord{has_flags ? 0 : sig, nA, nB, nC};
