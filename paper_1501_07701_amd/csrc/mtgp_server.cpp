@@ -23,6 +23,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -130,7 +131,12 @@ struct Server {
     std::condition_variable cv_work;   // wakes the loop
     std::condition_variable cv_done;   // wakes waiters
     std::unordered_map<uint64_t, Req> reqs;
-    std::deque<uint64_t> pending;      // tickets in submission order
+    std::list<uint64_t> pending;       // tickets in submission order
+    // set by whatever can make a queued request admissible (a submission,
+    // released pool bytes, a stream leaving the GPU); admission passes run
+    // only when it is set
+    bool admit_dirty = true;
+    std::vector<uint8_t> blocked_mark;  // per stream, within one admission pass
     std::unordered_map<int32_t, std::deque<uint64_t>> per_stream;
     std::vector<uint8_t> stream_busy;
     std::unique_ptr<Pool> pool;
@@ -150,13 +156,13 @@ struct Server {
     std::vector<std::vector<uint64_t>> ready;
 
     void admit_locked() {
-        if (pending.empty()) return;
+        if (pending.empty() || !admit_dirty) return;
+        admit_dirty = false;
         const int cap = opts.max_batch_items;
         std::vector<int32_t> touched;
-        auto is_blocked = [&](int32_t s) {
-            return std::find(touched.begin(), touched.end(), s) != touched.end();
-        };
-        for (auto it = pending.begin(); it != pending.end() && (int)ready.size() < cap;) {
+        auto is_blocked = [&](int32_t s) { return blocked_mark[(size_t)s] != 0; };
+        auto it = pending.begin();
+        for (; it != pending.end() && (int)ready.size() < cap;) {
             auto rit = reqs.find(*it);
             if (rit == reqs.end() || rit->second.state != R_QUEUED) {
                 it = pending.erase(it);
@@ -179,7 +185,8 @@ struct Server {
             }
             uint64_t off = 0;
             if (!pool->alloc(bytes, &off)) {
-                touched.push_back(s);  // keep this stream's order: try later
+                blocked_mark[(size_t)s] = 1;  // keep this stream's order: try later
+                touched.push_back(s);
                 ++it;
                 continue;
             }
@@ -200,6 +207,8 @@ struct Server {
             ready.push_back(std::move(group));
             it = pending.erase(it);
         }
+        if (it != pending.end()) admit_dirty = true;  // stopped at a full batch
+        for (int32_t s : touched) blocked_mark[(size_t)s] = 0;
     }
 
     // Called with `lk` held; releases it while the batch is planned and
@@ -258,6 +267,7 @@ struct Server {
         r.state = st;
         r.t_done = now();
         stream_busy[r.stream] = 0;
+        admit_dirty = true;
     }
 
     // Scan flags of in-flight items; retire finished slots.
@@ -404,6 +414,7 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states, int state_strid
     S.t0 = Clock::now();
     (void)hipGetDevice(&S.device);
     S.stream_busy.assign((size_t)n_streams, 0);
+    S.blocked_mark.assign((size_t)n_streams, 0);
     S.slots.resize((size_t)o.max_inflight_batches);
     int rc = MTGP_OK;
     for (int i = 0; i < o.max_inflight_batches && rc == MTGP_OK; ++i) {
@@ -457,6 +468,7 @@ int mtgp_submit(mtgp_server *srv, int32_t stream_id, uint64_t count, int dtype,
     auto &q = S.per_stream[stream_id];
     q.push_back(r.ticket);
     S.pending.push_back(r.ticket);
+    S.admit_dirty = true;
     S.reqs.emplace(r.ticket, r);
     ++S.queued;
     *ticket = r.ticket;
@@ -495,6 +507,7 @@ int mtgp_submit_many(mtgp_server *srv, const int32_t *stream_ids, const uint64_t
         r.t_submit = t;
         S.per_stream[r.stream].push_back(r.ticket);
         S.pending.push_back(r.ticket);
+        S.admit_dirty = true;
         tickets[i] = r.ticket;
         S.reqs.emplace(r.ticket, r);
         ++S.queued;
@@ -562,6 +575,7 @@ int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int
                 r.t_submit = t;
                 S.per_stream[r.stream].push_back(r.ticket);
                 S.pending.push_back(r.ticket);
+                S.admit_dirty = true;
                 tickets[(size_t)next] = r.ticket;
                 S.reqs.emplace(r.ticket, r);
                 ++S.queued;
@@ -584,6 +598,7 @@ int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int
                         h_stages_ns[3 * (size_t)i + 2] = r.t_done - r.t_launch;
                     }
                     if (r.bytes) S.pool->release(r.off, r.bytes);
+                    S.admit_dirty = true;
                     S.reqs.erase(it);
                     ++finished;
                     S.cv_work.notify_one();
@@ -639,6 +654,7 @@ int mtgp_release(mtgp_server *srv, uint64_t ticket) {
     } else if (r.state == R_DONE || r.state == R_FAILED) {
         if (r.bytes) S.pool->release(r.off, r.bytes);
     }
+    S.admit_dirty = true;
     S.reqs.erase(it);
     S.cv_work.notify_one();
     return MTGP_OK;
