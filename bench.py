@@ -764,7 +764,8 @@ def run_c5(args):
     line = _common(args, sat_outputs_s / 1e9, "G outputs/s", 0.0,
                    {"workload": cfg["name"], "mexp": mexp, "resident_streams": n_streams,
                     "requests_per_rate": n_req, "mean_request_outputs": round(float(L.mean())),
-                    "inflight_batches": args.inflight, "batch_window_us": args.batch_window_us},
+                    "inflight_batches": args.inflight, "batch_window_us": args.batch_window_us,
+                    "max_batch_items": 128},
                    None, None,
                    {"saturation_req_per_s": round(lam_sat, 1),
                     "warmup_polynomials_s": round(t_warm, 2),
