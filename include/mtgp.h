@@ -29,6 +29,12 @@
  *     read during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     Calls are asynchronous and stream-ordered unless stated otherwise.
+ *     The calls that synchronise are set-up and host-transfer calls
+ *     (mtgp_init_states, mtgp_load_params, mtgp_batch_workspace_query,
+ *     mtgp_stream_polynomials, mtgp_autotune, mtgp_state_export/import,
+ *     mtgp_batch_errors, mtgp_batch_phase_times), mtgp_generate_batch when
+ *     it first builds a stream's jump-ahead polynomial, and the server's
+ *     mtgp_wait, mtgp_server_replay and mtgp_server_destroy.
  *   - Every function returns MTGP_OK (0) or a negative MTGP_E* code; nothing
  *     is launched when validation fails.  mtgp_last_error_detail() gives a
  *     thread-local human-readable reason for the last failure.
@@ -84,6 +90,7 @@ int mtgp_state_words(uint32_t mexp);
 int mtgp_check_params(const mtgp_params *h_params, int n_streams);
 
 /* Seed status -> initial state for every stream (Sec. 3.1, Sec. 5.1).
+ * Like mtgp_load_params, this is a set-up call that synchronises.
  *   h_params   : n_streams parameter sets (validated first).
  *   h_seeds    : n_streams seeds (uint32).
  *   d_params   : device buffer of n_streams * MTGP_DEVICE_PARAM_BYTES bytes,
@@ -105,7 +112,10 @@ int mtgp_seed_states(const void *d_params, uint32_t *d_states, int state_stride,
                      int n_streams, void *stream);
 
 /* Uploads parameter sets without touching states (e.g. before importing
- * checkpointed states).  Same layout and synchronisation as above. */
+ * checkpointed states).  Same layout and synchronisation as above.  The
+ * stored seeds are 0 (mtgp_seed_states then seeds every stream with 0);
+ * jump-ahead polynomials are built from the streams' states as found in
+ * d_states when they are first split. */
 int mtgp_load_params(const mtgp_params *h_params, int n_streams,
                      void *d_params, void *stream);
 
@@ -138,9 +148,11 @@ typedef struct mtgp_work {
 size_t mtgp_batch_workspace_bytes(int n_items);
 
 /* Workspace bytes that let this batch split every long stream into the
- * jump-ahead segments the current tuning asks for.  May build the streams'
- * jump-ahead data first (device work + host polynomial arithmetic, once per
- * parameter set and stream), so it can synchronise the device. */
+ * jump-ahead segments the current tuning asks for.  Builds the seeded
+ * streams' jump-ahead polynomials first (device work + host polynomial
+ * arithmetic, once per stream; synchronises the device).  Streams whose
+ * polynomial must come from their current state (after an import) are
+ * sized for the largest polynomial. */
 int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items,
                                int n_items, size_t *bytes);
 
@@ -155,19 +167,32 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items,
  * batch's target (see mtgp_tuning) is cut into segments that run in
  * parallel.  Their start states are XOR-combinations of the stream's first
  * words given by x^(J-1) mod p, p an annihilating polynomial of the
- * stream's word sequence found by Berlekamp-Massey and checked on the device
- * (built once per stream, from its seed status).  Each segment checks its
- * final state against the next segment's start; mismatches are counted in
- * the workspace (mtgp_batch_errors).  Outputs are identical to unsplit
- * generation.  Streams whose state was imported from elsewhere may fail the
- * check: split batches then report errors and such streams should be run
- * with jump_target_steps = 0.
+ * stream's word sequence found by Berlekamp-Massey and checked on the
+ * device.  p is built once per stream from its seed status's orbit while
+ * the stream's state was last set by seeding, and from the orbit of its
+ * current state after mtgp_load_params or mtgp_state_import (rebuilt as
+ * the lcm with the old one).  Each segment checks its final state against
+ * the next segment's start; if any check fails (a state written into
+ * d_states behind the library's back, or overwritten workspace contents),
+ * the device regenerates the whole request in order from its start state
+ * before the call's kernels end, so outputs and final states are always
+ * those of unsplit generation.  Such repairs are counted in the workspace
+ * (mtgp_batch_errors), which also makes the library rebuild those streams'
+ * polynomials from their current states.
  *
  * d_workspace: workspace_bytes (>= mtgp_batch_workspace_bytes(n_items)) of
  * device memory the caller owns, 256-byte aligned; splitting is reduced to
- * fit.  The library caches the uploaded plan in it: do not modify it between
- * calls.  Asynchronous (the first call on a new parameter set may
- * synchronise while it builds jump-ahead data). */
+ * fit.  Its first 256 bytes hold claim counters, the repair count and
+ * phase timestamps.  Every call uploads the plan's item tables (an async
+ * copy from pinned host memory on `stream`, ahead of the kernels); the jump
+ * polynomials are uploaded only when the plan changes, so keep the
+ * workspace's contents between calls for speed (results do not depend on
+ * it).  Calls on one workspace must not overlap.
+ *
+ * Asynchronous, except that planning a stream's first split (or a split
+ * after an import) builds its polynomial: device work on `stream` plus
+ * host Berlekamp-Massey, which synchronises `stream` (milliseconds per
+ * stream; call mtgp_batch_workspace_query beforehand to do it up front). */
 int mtgp_generate_batch(const void *d_params, uint32_t *d_states,
                         int state_stride, const mtgp_work *h_items,
                         int n_items, void *d_workspace, size_t workspace_bytes,
@@ -187,9 +212,12 @@ int mtgp_set_phase_timing(int enable);
  * workspace holds no timestamps. */
 int mtgp_batch_phase_times(void *d_workspace, void *stream, double *h_us);
 
-/* Synchronises `stream`, returns in *n the number of jump-ahead segment
- * checks that failed in batches run on this workspace since the last call,
- * and resets the count. */
+/* Synchronises `stream`, returns in *n the number of requests that batches
+ * on this workspace regenerated after a failed jump-ahead segment check
+ * since the count was last read (zero when the library first saw the
+ * workspace), and resets it.  A nonzero count also marks the repaired
+ * streams (up to eight logged by the device, else every stream the last
+ * plan split) for a polynomial rebuild from their current states. */
 int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n);
 
 /* Launch tuning for one mexp: threads per stream (64 = one wave per stream,
@@ -234,7 +262,8 @@ int mtgp_autotune(const void *d_params, const uint32_t *d_states,
 /* Checkpoint: copy n_streams state rows device -> host (h_out holds
  * n_streams * N words, densely packed) and back.  Synchronise `stream`.
  * This is the paper's persistence of generator state in global memory
- * between launches (Sec. 2). */
+ * between launches (Sec. 2).  Imported streams get their jump-ahead
+ * polynomial rebuilt from the imported state when next split. */
 int mtgp_state_export(const void *d_params, const uint32_t *d_states,
                       int state_stride, int n_streams, uint32_t *h_out,
                       void *stream);
@@ -256,7 +285,9 @@ int mtgp_generate_workgroup(const void *d_params, uint32_t *d_states,
 
 /* Minimal polynomial of each stream's output word sequence from its seed
  * status (the polynomial the jump-ahead uses; Berlekamp-Massey on the host,
- * checked on the device to annihilate the word sequence).  For parameter
+ * checked on the device to annihilate the word sequence; for a stream
+ * whose states were imported it also covers the imported states' orbits,
+ * and it is -1 until such a stream was first split).  For parameter
  * sets from the Dynamic Creator it is the characteristic polynomial of the
  * generator, whose uniqueness across a set is what makes the streams
  * distinct (Sec. 3.2): equal polynomials flag duplicate generators.
@@ -340,18 +371,25 @@ int mtgp_release(mtgp_server *srv, uint64_t ticket);
  * bytes as soon as it completes, and blocks until all are done.
  * h_latency_ns[i] = completion - scheduled arrival; h_stages_ns (3n, may be
  * NULL) = queued, admitted-to-launch and running time of each request.
- * The results themselves are not kept. */
+ * d_keep (may be NULL): where d_keep[i] is not NULL, request i's result
+ * (counts[i] * 4 bytes) is copied there (device memory the caller owns)
+ * before its pool bytes are returned; other results are not kept. */
 int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns,
                        const int32_t *stream_ids, const uint64_t *counts,
                        const int *dtypes, int n, uint64_t *h_latency_ns,
-                       uint64_t *h_stages_ns);
+                       uint64_t *h_stages_ns, void *const *d_keep);
+/* Requests the server's batches regenerated on the device after a failed
+ * jump-ahead segment check (their results are exact), since creation. */
+int mtgp_server_repaired(mtgp_server *srv, uint64_t *n);
 /* Per-request timestamps in ns since server creation: submitted, admitted
  * (pool bytes granted), launched, completed (observed by the server). */
 int mtgp_request_times(mtgp_server *srv, uint64_t ticket, uint64_t *t_submit,
                        uint64_t *t_admit, uint64_t *t_launch,
                        uint64_t *t_done);
 /* Stops the loop; queued requests never admitted end as MTGP_ECANCELED,
- * in-flight launches are waited for. */
+ * in-flight launches are waited for, and threads blocked in mtgp_wait
+ * return (MTGP_ECANCELED for cancelled requests) before it frees the
+ * server.  No call may start on the server once destroy has begun. */
 int mtgp_server_destroy(mtgp_server *srv);
 
 const char *mtgp_strerror(int code);

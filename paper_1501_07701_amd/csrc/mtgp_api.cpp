@@ -191,6 +191,10 @@ static int upload_params(const mtgp_params *h, const uint32_t *seeds, int n, voi
     set->mexp = h[0].mexp;
     set->W.resize(n);
     set->lin.resize(n);
+    // seeded streams' jump-ahead polynomials come from their seed orbits;
+    // after a parameter reload the states come from elsewhere
+    set->seeded.assign((size_t)n, seeds ? 1 : 0);
+    set->dirty.assign((size_t)n, seeds ? 0 : 1);
     for (int k = 0; k < n; ++k) {
         uint32_t *b = &blob[(size_t)k * P_WORDS];
         b[P_MEXP] = h[k].mexp;
@@ -348,7 +352,9 @@ int mtgp_seed_states(const void *d_params, uint32_t *d_states, int state_stride,
                     ps->N);
     hipError_t e = launch_seed((const uint32_t *)d_params, d_states, (uint32_t)state_stride,
                                (uint32_t)n_streams, (hipStream_t)stream);
-    return e == hipSuccess ? MTGP_OK : hip_fail(e, "seed kernel");
+    if (e != hipSuccess) return hip_fail(e, "seed kernel");
+    note_states_seeded(*ps, n_streams);
+    return MTGP_OK;
 }
 
 int mtgp_load_params(const mtgp_params *h_params, int n_streams, void *d_params, void *stream) {
@@ -443,7 +449,11 @@ int mtgp_state_import(const void *d_params, uint32_t *d_states, int state_stride
                                     (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync(import)");
     e = hipStreamSynchronize((hipStream_t)stream);
-    return e == hipSuccess ? MTGP_OK : hip_fail(e, "hipStreamSynchronize(import)");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(import)");
+    // the imported states may lie outside the orbits the streams' jump-ahead
+    // polynomials annihilate: rebuild those from the states themselves
+    note_states_foreign(*ps, nullptr, n_streams);
+    return MTGP_OK;
 }
 
 int mtgp_generate_workgroup(const void *d_params, uint32_t *d_states, int state_stride,

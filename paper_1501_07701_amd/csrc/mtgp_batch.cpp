@@ -14,17 +14,28 @@
 //   C: every segment (the first one continues after the prefix up to
 //      c0*lseg), each checking its end state against the next segment's
 //      start state.
-// p is found once per stream from its seed status: Berlekamp-Massey on two
-// linear functionals of 2*mexp+127 words (lcm of the two), then checked on
-// the device over mexp further positions; if the check fails all 32 bit
-// functionals are used.  The orbit of a seeded state contains every later
-// state of that stream, so p stays valid as the stream advances or is
-// re-seeded.
+// p is built per stream from one orbit: Berlekamp-Massey on two linear
+// functionals of 2*mexp+127 words (lcm of the two), checked on the device
+// over mexp further positions, all 32 bit functionals if the check fails.
+// The orbit is the stream's seed status's while its state was last set by
+// seeding (the seed orbit holds every later state of the stream), else the
+// orbit of its current state (after mtgp_state_import or
+// mtgp_load_params); a stream whose state moved to a new orbit gets the lcm
+// of the old and the new polynomial.
+//
+// The segment checks make every split request exact whatever p is: if all
+// checks pass, each segment started from the true state (by induction from
+// the prefix); if one fails, the batch's last launch (one check item per
+// split request, after every segment has finished) regenerates the request
+// in order from its start state (kept by the prefix) and logs the stream,
+// which the host then rebuilds from its current state.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
+#include <list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -42,6 +53,7 @@ namespace mtgp {
 struct StreamJump {
     int status = 0;  // 1 usable, -1 never split this stream
     int D = 0;       // degree of the annihilating polynomial p
+    bool has_seed_orbit = false;  // p annihilates the seed status's orbit
     std::unique_ptr<poly::Modulus> mod;
     uint64_t lseg = 0;                       // segment length g is built for
     poly::Poly xl;                           // x^lseg mod p
@@ -50,8 +62,48 @@ struct StreamJump {
 };
 
 Staging::~Staging() {
+    if (pending && done) (void)hipEventSynchronize(done);  // a copy may still read host
     if (host) (void)hipHostFree(host);
     if (done) (void)hipEventDestroy(done);
+}
+
+static void size_tracking(ParamSet &ps) {
+    if (ps.jumps.size() != (size_t)ps.n) ps.jumps.resize((size_t)ps.n);
+    if (ps.seeded.size() != (size_t)ps.n) ps.seeded.resize((size_t)ps.n, 1);
+    if (ps.dirty.size() != (size_t)ps.n) ps.dirty.resize((size_t)ps.n, 0);
+}
+
+void note_states_seeded(ParamSet &ps, int n) {
+    std::lock_guard<std::mutex> lk(ps.jump_mu);
+    size_tracking(ps);
+    for (int k = 0; k < n && k < ps.n; ++k) {
+        ps.seeded[(size_t)k] = 1;
+        const StreamJump *sj = ps.jumps[(size_t)k].get();
+        if (sj && !(sj->status == 1 && sj->has_seed_orbit)) ps.dirty[(size_t)k] = 1;
+    }
+}
+
+void note_states_foreign(ParamSet &ps, const int32_t *streams, int n) {
+    std::lock_guard<std::mutex> lk(ps.jump_mu);
+    size_tracking(ps);
+    for (int i = 0; i < n; ++i) {
+        const int k = streams ? streams[i] : i;
+        if (k < 0 || k >= ps.n) continue;
+        ps.seeded[(size_t)k] = 0;
+        ps.dirty[(size_t)k] = 1;
+    }
+}
+
+void note_repairs(ParamSet &ps, const uint32_t *err_words, const std::vector<int32_t> &split) {
+    const uint32_t n = err_words[0], logged = err_words[1];
+    if (n == 0) return;
+    if (logged <= (uint32_t)HDR_LOG_MAX) {
+        std::vector<int32_t> ks;
+        for (uint32_t i = 0; i < logged; ++i) ks.push_back((int32_t)err_words[2 + i]);
+        note_states_foreign(ps, ks.data(), (int)ks.size());
+    } else {
+        note_states_foreign(ps, split.data(), (int)split.size());
+    }
 }
 
 template <class F>
@@ -120,18 +172,31 @@ struct DevBuf {
 };
 }  // namespace
 
-// Builds (once) the annihilating polynomial of every listed stream.
+// Builds the annihilating polynomial of every listed stream that has none
+// or whose state may have left the orbits its polynomial was built from:
+// from the seed status while the stream's state was last set by seeding,
+// else from its current state row (d_states; streams needing one are
+// skipped when d_states is NULL).  A rebuilt stream keeps the lcm of its
+// old and new polynomial.
 static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_params,
-                        const std::vector<int> &streams, const mtgp_tuning &tun,
-                        hipStream_t s) {
+                        const uint32_t *d_states, int stride, const std::vector<int> &streams,
+                        const mtgp_tuning &tun, hipStream_t s) {
     std::lock_guard<std::mutex> lk(ps->jump_mu);
-    if (ps->jumps.size() != (size_t)ps->n) ps->jumps.assign((size_t)ps->n, nullptr);
+    size_tracking(*ps);
+    std::vector<int> cand = streams;
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
     std::vector<int> todo;
-    for (int k : streams)
-        if (!ps->jumps[k]) todo.push_back(k);
+    std::vector<uint8_t> from_seed;
+    for (int k : cand) {
+        if (k < 0 || k >= ps->n) continue;
+        if (ps->jumps[(size_t)k] && !ps->dirty[(size_t)k]) continue;
+        const bool seedy = ps->seeded[(size_t)k] != 0;
+        if (!seedy && !d_states) continue;
+        todo.push_back(k);
+        from_seed.push_back(seedy ? 1 : 0);
+    }
     if (todo.empty()) return MTGP_OK;
-    std::sort(todo.begin(), todo.end());
-    todo.erase(std::unique(todo.begin(), todo.end()), todo.end());
 
     const int N = ps->N;
     const int mexp = (int)ps->mexp;
@@ -141,10 +206,13 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
     const int chunk = 512;
     hipError_t e;
     DevBuf d_seeded;
-    if ((e = d_seeded.alloc((size_t)ps->n * N * 4)) != hipSuccess) return hip_fail(e, "hipMalloc");
-    if ((e = launch_seed((const uint32_t *)d_params, (uint32_t *)d_seeded.p, (uint32_t)N,
-                         (uint32_t)ps->n, s)) != hipSuccess)
-        return hip_fail(e, "seed kernel");
+    if (std::find(from_seed.begin(), from_seed.end(), 1) != from_seed.end()) {
+        if ((e = d_seeded.alloc((size_t)ps->n * N * 4)) != hipSuccess)
+            return hip_fail(e, "hipMalloc");
+        if ((e = launch_seed((const uint32_t *)d_params, (uint32_t *)d_seeded.p, (uint32_t)N,
+                             (uint32_t)ps->n, s)) != hipSuccess)
+            return hip_fail(e, "seed kernel");
+    }
     const int cn = std::min<int>(chunk, (int)todo.size());
     DevBuf d_raw, d_out, d_items, d_counter, d_jitems, d_poly, d_vout;
     if ((e = d_raw.alloc((size_t)cn * R * 4)) != hipSuccess ||
@@ -168,7 +236,9 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
             b.mode = MODE_RAW;
             b.count = (uint64_t)(R - N);
             b.out = (uint64_t)(uintptr_t)((uint32_t *)d_out.p + (size_t)j * (R - N));
-            b.state_in = (uint64_t)(uintptr_t)((uint32_t *)d_seeded.p + (size_t)k * N);
+            b.state_in = from_seed[c0 + j]
+                             ? (uint64_t)(uintptr_t)((uint32_t *)d_seeded.p + (size_t)k * N)
+                             : (uint64_t)(uintptr_t)(d_states + (size_t)k * stride);
             b.raw = (uint64_t)(uintptr_t)((uint32_t *)d_raw.p + (size_t)j * R);
         }
         if ((e = hipMemcpyAsync(d_items.p, items.data(), items.size() * sizeof(BatchItem),
@@ -250,17 +320,31 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
         }
         std::vector<std::shared_ptr<StreamJump>> built((size_t)m);
         parallel_for(m, [&](int j) {
+            const int k = todo[c0 + j];
+            const StreamJump *old = ps->jumps[(size_t)k].get();
+            const bool old_ok = old && old->status == 1;
             auto sj = std::make_shared<StreamJump>();
+            sj->status = -1;
             if (ok[j]) {
-                sj->status = 1;
-                sj->D = poly::degree(P[j]);
-                sj->mod = std::make_unique<poly::Modulus>(P[j]);
-            } else {
-                sj->status = -1;
+                // every polynomial here divides the minimal polynomial of the
+                // transition on its image (dimension mexp), so the lcm keeps
+                // degree <= mexp
+                poly::Poly p = old_ok ? poly::lcm(old->mod->p, P[j]) : P[j];
+                const int D = poly::degree(p);
+                if (D >= 1 && D <= mexp) {
+                    sj->status = 1;
+                    sj->D = D;
+                    sj->mod = std::make_unique<poly::Modulus>(p);
+                    sj->has_seed_orbit = from_seed[c0 + j] || (old_ok && old->has_seed_orbit);
+                }
             }
             built[j] = sj;
         });
-        for (int j = 0; j < m; ++j) ps->jumps[todo[c0 + j]] = built[j];
+        for (int j = 0; j < m; ++j) {
+            const int k = todo[c0 + j];
+            ps->jumps[(size_t)k] = built[j];
+            ps->dirty[(size_t)k] = 0;
+        }
     }
     return MTGP_OK;
 }
@@ -309,11 +393,13 @@ struct Seg {
     int C = 1;           // segments (1 = not split)
     uint64_t lseg = 0;
     uint64_t c0 = 0;
-    StreamJump *sj = nullptr;
+    int D = 0;           // degree of the stream's polynomial
+    int Dsize = 0;       // degree the workspace is sized for (>= D)
+    std::shared_ptr<StreamJump> sj;
 };
 
 struct Layout {
-    size_t off_A = 0, off_B = 0, off_C = 0, off_cd = 0, off_poly = 0, up_end = 0;
+    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, off_rec = 0, off_poly = 0, up_end = 0;
     size_t off_raw = 0, off_js = 0, total = 0;
 };
 
@@ -321,9 +407,9 @@ size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 }  // namespace
 
 size_t batch_min_ws_bytes(int n_items) {
-    // header + A/B (none) + C items + countdowns
-    return 256 + al256((size_t)std::max(n_items, 0) * sizeof(BatchItem)) +
-           al256((size_t)std::max(n_items, 0) * 4);
+    // header + one item per request (no split: no prefix, jump or check
+    // items, no request records)
+    return HDR_BYTES + al256((size_t)std::max(n_items, 0) * sizeof(BatchItem));
 }
 
 // The dependent-step target of a batch: the tuning's jump_target_steps is
@@ -362,16 +448,16 @@ static uint64_t segment_length(uint64_t v) {
     return (v >> e) << e;
 }
 
-// Splits a request when it needs more than T dependent steps and the
-// stream's jump data is usable.
-static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_t T,
-                   const mtgp_tuning &t, Seg &g) {
+// Splits a request when it needs more than T dependent steps, for a stream
+// polynomial of degree D (D < 1: never).
+static void decide(const ParamSet &ps, const Request &r, int D, uint64_t T, const mtgp_tuning &t,
+                   Seg &g) {
     g.C = 1;
-    g.sj = nullptr;
-    if (!T || !sj || sj->status != 1) return;
+    g.D = g.Dsize = 0;
+    if (!T || D < 1) return;
     const uint64_t so = step_outputs(ps, r.stream, t);
     if ((r.count + so - 1) / so <= T) return;
-    const uint64_t P = (uint64_t)sj->D + 1;
+    const uint64_t P = (uint64_t)D + 1;
     const uint64_t lseg = segment_length(T * so);
     const uint64_t c0 = (P + 1 + lseg - 1) / lseg;   // segment 0 keeps >= 1 output past P
     const uint64_t cend = (r.count + lseg - 1) / lseg;
@@ -379,7 +465,7 @@ static void decide(const ParamSet &ps, const Request &r, StreamJump *sj, uint64_
     g.C = (int)(1 + cend - c0);
     g.lseg = lseg;
     g.c0 = c0;
-    g.sj = sj;
+    g.D = g.Dsize = D;
 }
 
 static bool wants_split(const ParamSet &ps, const Request &r, uint64_t T, const mtgp_tuning &t) {
@@ -388,7 +474,7 @@ static bool wants_split(const ParamSet &ps, const Request &r, uint64_t T, const 
     return (r.count + so - 1) / so > T && r.count > (uint64_t)ps.mexp + 128;
 }
 
-static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_t n_req) {
+static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs) {
     size_t nA = 0, nB = 0, nC = 0, poly_words = 0, raw_words = 0, js_words = 0;
     for (const Seg &g : segs) {
         if (g.C <= 1) {
@@ -398,16 +484,17 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_
         ++nA;
         nB += ((size_t)g.C - 1 + JUMP_BLOCK - 1) / JUMP_BLOCK * JUMP_BLOCK;
         nC += (size_t)g.C;
-        poly_words += ((size_t)g.C - 1) * (((size_t)g.sj->D + 31) / 32);
-        raw_words += ((size_t)ps.N + (size_t)g.sj->D + 1 + 63) / 64 * 64;
+        poly_words += ((size_t)g.C - 1) * (((size_t)g.Dsize + 31) / 32);
+        raw_words += ((size_t)ps.N + (size_t)g.Dsize + 1 + 63) / 64 * 64;
         js_words += (size_t)g.C * (size_t)ps.N;
     }
     Layout L;
-    L.off_A = 256;
+    L.off_A = HDR_BYTES;
     L.off_B = L.off_A + al256(nA * sizeof(BatchItem));
     L.off_C = L.off_B + al256(nB * sizeof(JumpItem));
-    L.off_cd = L.off_C + al256(nC * sizeof(BatchItem));
-    L.off_poly = L.off_cd + al256(n_req * 4);
+    L.off_F = L.off_C + al256(nC * sizeof(BatchItem));
+    L.off_rec = L.off_F + al256(nA * sizeof(BatchItem));
+    L.off_poly = L.off_rec + al256(nA * sizeof(ReqRec));
     L.up_end = L.off_poly + al256(poly_words * 4);
     L.off_raw = L.up_end;
     L.off_js = L.off_raw + al256(raw_words * 4);
@@ -415,9 +502,9 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs, size_
     return L;
 }
 
-// Pinned staging for the uploaded plan: acquire waits until the previous
-// upload from this buffer has been consumed, then hands out at least n
-// bytes; the plan is written in place and commit copies it to the device.
+// Pinned staging for the uploaded plan: acquire waits until every upload
+// from this buffer has been consumed, then hands out at least n bytes; the
+// plan is written in place and stage_copy uploads a byte range of it.
 static int stage_acquire(Staging &st, size_t n, uint8_t **out) {
     if (st.pending) {
         hipError_t e = hipEventSynchronize(st.done);
@@ -443,9 +530,9 @@ static int stage_acquire(Staging &st, size_t n, uint8_t **out) {
     return MTGP_OK;
 }
 
-static int stage_commit(Staging &st, size_t n, void *d_dst, hipStream_t s) {
-    if (n == 0) return MTGP_OK;
-    hipError_t e = hipMemcpyAsync(d_dst, st.host, n, hipMemcpyHostToDevice, s);
+static int stage_copy(Staging &st, size_t lo, size_t hi, char *d_base, hipStream_t s) {
+    if (hi <= lo) return MTGP_OK;
+    hipError_t e = hipMemcpyAsync(d_base + lo, st.host + lo, hi - lo, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(work list)");
     e = hipEventRecord(st.done, s);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -453,18 +540,30 @@ static int stage_commit(Staging &st, size_t n, void *d_dst, hipStream_t s) {
     return MTGP_OK;
 }
 
-// What was last uploaded to a workspace, so identical calls replay at once.
 namespace {
-struct WsRecord {
-    uint64_t sig = 0;
-    uint32_t nA = 0, nB = 0, nC = 0;
-};
-std::mutex g_ws_mu;
-std::map<const void *, WsRecord> g_ws;
-
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
     return h;
+}
+
+// Workspaces the library has planned for, most recently used first; an
+// evicted entry lives on until its last call returns.
+std::mutex g_ws_mu;
+std::list<std::pair<const void *, std::shared_ptr<WsState>>> g_ws;
+constexpr size_t kMaxWorkspaces = 64;
+
+std::shared_ptr<WsState> ws_state(const void *d_ws, bool create) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    for (auto it = g_ws.begin(); it != g_ws.end(); ++it) {
+        if (it->first == d_ws) {
+            g_ws.splice(g_ws.begin(), g_ws, it);
+            return g_ws.front().second;
+        }
+    }
+    if (!create) return nullptr;
+    g_ws.emplace_front(d_ws, std::make_shared<WsState>());
+    if (g_ws.size() > kMaxWorkspaces) g_ws.pop_back();
+    return g_ws.front().second;
 }
 
 struct GraphKey {
@@ -472,11 +571,11 @@ struct GraphKey {
     uint32_t nA, nB, nC;
     const void *params;
     int N, tps, k, wg, win, device;
-    bool stamps;
+    bool stamps, errs;
     bool operator<(const GraphKey &o) const {
-        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, win, device, stamps) <
+        return std::tie(ws, nA, nB, nC, params, N, tps, k, wg, win, device, stamps, errs) <
                std::tie(o.ws, o.nA, o.nB, o.nC, o.params, o.N, o.tps, o.k, o.wg, o.win,
-                        o.device, o.stamps);
+                        o.device, o.stamps, o.errs);
     }
 };
 std::atomic<bool> g_stamps{false};  // phase timestamps in every batch call
@@ -490,10 +589,22 @@ bool graphs_enabled() {
 }
 }  // namespace
 
-// Launches the three phases of a planned batch on `s`.
-static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, uint32_t nA,
-                         uint32_t nB, uint32_t nC, const Layout &L, const mtgp_tuning &t,
-                         hipStream_t s, bool stamps) {
+// Tag of a workspace header: derived from its address and a per-process
+// salt, so reused memory at the same address is recognised as fresh unless
+// it still holds a header this process wrote there.
+static uint64_t header_tag(const void *d_ws) {
+    static const uint64_t salt = mix((uint64_t)(uintptr_t)&salt,
+                                     (uint64_t)std::chrono::steady_clock::now()
+                                         .time_since_epoch()
+                                         .count());
+    uint64_t t = mix(salt, (uint64_t)(uintptr_t)d_ws);
+    return t ? t : 1;
+}
+
+// Launches the phases of the workspace's planned batch on `s`: header,
+// prefix items, jump evaluation, segments, request checks.
+static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, const WsState &w,
+                         const mtgp_tuning &t, hipStream_t s, bool stamps, bool clear_errors) {
     uint32_t *hdr = (uint32_t *)ws;
     uint64_t *ts = (uint64_t *)(ws + HDR_STAMP_BYTE);
     auto stamp = [&](int i) -> int {
@@ -501,44 +612,229 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, uin
         const hipError_t e = launch_stamp(ts + i, s);
         return e == hipSuccess ? MTGP_OK : hip_fail(e, "stamp kernel");
     };
-    int rc0 = stamp(0);
-    if (rc0) return rc0;
+    hipError_t e;
+    if ((e = launch_header(hdr, header_tag(ws), clear_errors, s)) != hipSuccess)
+        return hip_fail(e, "header kernel");
+    int rc = stamp(0);
+    if (rc) return rc;
     LaunchArgs a{};
     a.params = (const uint32_t *)d_params;
-    a.err = hdr + 2;
+    a.err = hdr + HDR_ERR;
     a.persistent = true;
     a.num_cus = device_cus();
     a.stream = s;
-    hipError_t e;
-    if (nA) {
-        if ((e = launch_reset(hdr + 0, s)) != hipSuccess) return hip_fail(e, "reset kernel");
-        a.items = (const BatchItem *)(ws + L.off_A);
-        a.n_items = nA;
+    if (w.nA) {
+        a.items = (const BatchItem *)(ws + w.off_A);
+        a.n_items = w.nA;
         a.counter = hdr + 0;
-        int rc = launch_tuned(ps.N, t, a);
-        if (rc) return rc;
+        if ((rc = launch_tuned(ps.N, t, a))) return rc;
     }
-    if ((rc0 = stamp(1))) return rc0;
-    if (nB) {
-        if ((e = launch_jump((const JumpItem *)(ws + L.off_B), nB, device_cus(), s)) !=
+    if ((rc = stamp(1))) return rc;
+    if (w.nB) {
+        if ((e = launch_jump((const JumpItem *)(ws + w.off_B), w.nB, device_cus(), s)) !=
             hipSuccess)
             return hip_fail(e, "jump kernel");
     }
-    if ((rc0 = stamp(2))) return rc0;
-    if ((e = launch_reset(hdr + 1, s)) != hipSuccess) return hip_fail(e, "reset kernel");
-    a.items = (const BatchItem *)(ws + L.off_C);
-    a.n_items = nC;
+    if ((rc = stamp(2))) return rc;
+    a.items = (const BatchItem *)(ws + w.off_C);
+    a.n_items = w.nC;
     a.counter = hdr + 1;
-    const int rc = launch_tuned(ps.N, t, a);
-    if (rc) return rc;
+    if ((rc = launch_tuned(ps.N, t, a))) return rc;
+    if (w.nF) {  // request checks of the split requests
+        a.items = (const BatchItem *)(ws + w.off_F);
+        a.n_items = w.nF;
+        a.counter = hdr + HDR_FIX_CLAIM;
+        if ((rc = launch_tuned(ps.N, t, a))) return rc;
+    }
     return stamp(3);
+}
+
+// Writes the plan of `reqs` into the pinned image of w (byte offsets as in
+// the workspace) and records where its parts lie.
+static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
+                      uint32_t *d_states, int stride, const std::vector<Request> &reqs,
+                      char *ws, size_t ws_bytes, hipStream_t s, const mtgp_tuning &t,
+                      WsState &w) {
+    const int N = ps->N;
+    std::vector<Seg> segs(reqs.size());
+    std::vector<int> want;
+    uint64_t T = effective_target(*ps, reqs, t);
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        segs[i].req = (int)i;
+        if (wants_split(*ps, reqs[i], T, t)) want.push_back(reqs[i].stream);
+    }
+    if (!want.empty()) {
+        int rc = ensure_jumps(ps, d_params, d_states, stride, want, t, s);
+        if (rc) return rc;
+    }
+    // snapshot of the streams' jump data (an entry may be replaced by a
+    // rebuild meanwhile; the snapshot keeps this plan's alive)
+    std::vector<std::shared_ptr<StreamJump>> sjs(reqs.size());
+    {
+        std::lock_guard<std::mutex> lk(ps->jump_mu);
+        if (ps->jumps.size() == (size_t)ps->n)
+            for (size_t i = 0; i < reqs.size(); ++i) sjs[i] = ps->jumps[reqs[i].stream];
+    }
+    // plan, doubling the target until the workspace fits
+    Layout L;
+    while (true) {
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            const int D = (sjs[i] && sjs[i]->status == 1) ? sjs[i]->D : 0;
+            decide(*ps, reqs[i], D, T, t, segs[i]);
+            segs[i].sj = segs[i].C > 1 ? sjs[i] : nullptr;
+        }
+        L = layout_for(*ps, segs);
+        if (L.total <= ws_bytes || !T) break;
+        T *= 2;
+        if (T > (1ull << 40)) T = 0;
+    }
+    if (L.total > ws_bytes)
+        return fail(MTGP_EINVAL, "workspace of %zu bytes too small (need %zu)", ws_bytes,
+                    L.total);
+    // polynomials: only streams whose cache lacks them (a thread per
+    // stream costs more than a batch of cached lookups)
+    std::vector<Seg *> split;
+    for (Seg &g : segs)
+        if (g.C > 1 && !g_ready(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1)))
+            split.push_back(&g);
+    parallel_for((int)split.size(), [&](int i) {
+        const Seg &g = *split[i];
+        ensure_g(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1));
+    });
+
+    // the image of [HDR_BYTES, up_end): item tables, request records,
+    // polynomials (every byte that is read is written; the alignment gaps
+    // between tables are never read).  The header is never uploaded.
+    uint8_t *img = nullptr;
+    if (int rc = stage_acquire(w.stage, L.up_end, &img)) return rc;
+    auto at = [&](size_t off) { return img + off; };
+    std::vector<std::pair<uint64_t, BatchItem>> A, C;
+    std::vector<JumpItem> B;
+    std::vector<BatchItem> F;
+    std::vector<int32_t> split_streams;
+    size_t raw_off = L.off_raw, js_off = L.off_js, poly_off = L.off_poly;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Request &r = reqs[i];
+        const Seg &g = segs[i];
+        const uint32_t mode = r.dtype == MTGP_F32 ? MODE_F32 : 0u;
+        uint32_t *row = d_states + (size_t)r.stream * stride;
+        const uint64_t so = step_outputs(*ps, r.stream, t);
+        auto base_item = [&](uint64_t count, uint64_t out_off) {
+            BatchItem b;
+            std::memset(&b, 0, sizeof b);
+            b.stream = (uint32_t)r.stream;
+            b.mode = mode;
+            b.count = count;
+            b.out = (uint64_t)(uintptr_t)((char *)r.d_out + out_off * 4);
+            return b;
+        };
+        if (g.C <= 1) {
+            BatchItem b = base_item(r.count, 0);
+            b.state_in = b.state_out = (uint64_t)(uintptr_t)row;
+            b.flag = r.flag;
+            C.emplace_back((r.count + so - 1) / so, b);
+            continue;
+        }
+        // request record and check item of a split request
+        const size_t ri = F.size();
+        ReqRec *rc = (ReqRec *)at(L.off_rec) + ri;
+        const uint64_t rec_dev = (uint64_t)(uintptr_t)(ws + L.off_rec + ri * sizeof(ReqRec));
+        split_streams.push_back(r.stream);
+        const int D = g.D;
+        const uint64_t P = (uint64_t)D + 1;
+        uint32_t *raw = (uint32_t *)(ws + raw_off);
+        raw_off += ((size_t)N + (size_t)g.Dsize + 1 + 63) / 64 * 64 * 4;
+        uint32_t *js = (uint32_t *)(ws + js_off);  // C states of N words
+        js_off += (size_t)g.C * N * 4;
+        std::memset(rc, 0, sizeof *rc);
+        rc->stream = (uint32_t)r.stream;
+        rc->mode = mode;
+        rc->count = r.count;
+        rc->out = (uint64_t)(uintptr_t)r.d_out;
+        rc->orig = (uint64_t)(uintptr_t)raw;  // x_0 .. x_{N-1}: the start state
+        rc->row = (uint64_t)(uintptr_t)row;
+        BatchItem f = base_item(0, 0);
+        f.mode = MODE_FIXUP | mode;
+        f.rec = rec_dev;
+        f.flag = r.flag;
+        F.push_back(f);
+        // A: prefix
+        BatchItem a = base_item(P, 0);
+        a.mode |= MODE_RAW;
+        a.state_in = (uint64_t)(uintptr_t)row;
+        a.state_out = (uint64_t)(uintptr_t)js;
+        a.raw = (uint64_t)(uintptr_t)raw;
+        A.emplace_back((P + so - 1) / so, a);
+        // B: jumps, segment k >= 1 starts at output (c0+k-1)*lseg and
+        // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words
+        const size_t pw = ((size_t)D + 31) / 32;
+        for (int k = 1; k < g.C; ++k) {
+            const uint64_t c = g.c0 + (uint64_t)k - 1;
+            JumpItem j;
+            j.raw = (uint64_t)(uintptr_t)raw;
+            j.poly = (uint64_t)(uintptr_t)(ws + poly_off);
+            j.out = (uint64_t)(uintptr_t)(js + (size_t)k * N);
+            j.nbits = (uint32_t)D;
+            j.m = (uint32_t)N;
+            std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
+            poly_off += pw * 4;
+            B.push_back(j);
+        }
+        while (B.size() % JUMP_BLOCK) {  // pad this stream's block
+            JumpItem z;
+            std::memset(&z, 0, sizeof z);
+            B.push_back(z);
+        }
+        // C: segments; every one but the last checks its end state against
+        // the next one's jumped start
+        for (int k = 0; k < g.C; ++k) {
+            const uint64_t c = k == 0 ? 0 : g.c0 + (uint64_t)k - 1;
+            const uint64_t start = k == 0 ? P : c * g.lseg;
+            const uint64_t end = std::min<uint64_t>(r.count, k == 0 ? g.c0 * g.lseg
+                                                                    : (c + 1) * g.lseg);
+            BatchItem b = base_item(end - start, start);
+            b.state_in = (uint64_t)(uintptr_t)(js + (size_t)k * N);
+            if (k + 1 < g.C) {
+                b.mode |= MODE_VERIFY;
+                b.verify = (uint64_t)(uintptr_t)(js + (size_t)(k + 1) * N);
+                b.rec = rec_dev;
+            } else {
+                b.state_out = (uint64_t)(uintptr_t)row;
+            }
+            C.emplace_back((end - start + so - 1) / so, b);
+        }
+    }
+    auto lpt = [](const auto &x, const auto &y) { return x.first > y.first; };
+    std::stable_sort(A.begin(), A.end(), lpt);
+    std::stable_sort(C.begin(), C.end(), lpt);
+    for (size_t i = 0; i < A.size(); ++i)
+        std::memcpy(at(L.off_A) + i * sizeof(BatchItem), &A[i].second, sizeof(BatchItem));
+    if (!B.empty()) std::memcpy(at(L.off_B), B.data(), B.size() * sizeof(JumpItem));
+    for (size_t i = 0; i < C.size(); ++i)
+        std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].second, sizeof(BatchItem));
+    if (!F.empty()) std::memcpy(at(L.off_F), F.data(), F.size() * sizeof(BatchItem));
+    w.nA = (uint32_t)A.size();
+    w.nB = (uint32_t)B.size();
+    w.nC = (uint32_t)C.size();
+    w.nF = (uint32_t)F.size();
+    w.off_A = L.off_A;
+    w.off_B = L.off_B;
+    w.off_C = L.off_C;
+    w.off_F = L.off_F;
+    w.tables_end = L.off_poly;
+    w.up_end = L.up_end;
+    w.ps = ps;
+    w.split_streams = std::move(split_streams);
+    return MTGP_OK;
 }
 
 int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
               int stride, const std::vector<Request> &reqs, void *d_ws, size_t ws_bytes,
-              hipStream_t s, const mtgp_tuning &t, bool use_graph, Staging &stage) {
+              hipStream_t s, const mtgp_tuning &t, bool use_graph, WsState &w,
+              bool per_call_errors) {
     if (reqs.empty()) return MTGP_OK;
-    bool has_flags = false;
+    char *ws = (char *)d_ws;
+    hipError_t e;
     uint64_t sig = mix(0x51ull, (uint64_t)(uintptr_t)d_params);
     sig = mix(sig, ps->generation);
     sig = mix(sig, (uint64_t)(uintptr_t)d_states);
@@ -551,192 +847,50 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         sig = mix(sig, ((uint64_t)(uint32_t)r.stream << 32) | r.dtype);
         sig = mix(sig, r.count);
         sig = mix(sig, (uint64_t)(uintptr_t)r.d_out);
-        has_flags |= r.flag != 0;
+        sig = mix(sig, r.flag);
     }
-    char *ws = (char *)d_ws;
-    Layout L;
-    uint32_t nA = 0, nB = 0, nC = 0;
-    bool cached = false;
+    if (sig == 0) sig = 1;  // 0 marks "no plan"
+    // a request on a stream whose polynomial is to be rebuilt replans
+    bool dirty = false;
     {
-        std::lock_guard<std::mutex> lk(g_ws_mu);
-        auto it = g_ws.find(d_ws);
-        if (!has_flags && it != g_ws.end() && it->second.sig == sig) {
-            cached = true;
-            nA = it->second.nA;
-            nB = it->second.nB;
-            nC = it->second.nC;
-        }
-    }
-    std::vector<Seg> segs(reqs.size());
-    if (!cached) {
-        // which requests want splitting at the tuning's target
-        const int N = ps->N;
-        std::vector<int> want;
-        uint64_t T = effective_target(*ps, reqs, t);
-        for (size_t i = 0; i < reqs.size(); ++i) {
-            segs[i].req = (int)i;
-            if (wants_split(*ps, reqs[i], T, t)) want.push_back(reqs[i].stream);
-        }
-        if (!want.empty()) {
-            int rc = ensure_jumps(ps, d_params, want, t, s);
-            if (rc) return rc;
-        }
-        // snapshot of the streams' jump data (entries are built once and
-        // never replaced while the parameter set lives)
-        std::vector<StreamJump *> sjs(reqs.size(), nullptr);
-        {
-            std::lock_guard<std::mutex> lk(ps->jump_mu);
-            if (ps->jumps.size() == (size_t)ps->n)
-                for (size_t i = 0; i < reqs.size(); ++i) sjs[i] = ps->jumps[reqs[i].stream].get();
-        }
-        // plan, doubling the target until the workspace fits
-        while (true) {
-            for (size_t i = 0; i < reqs.size(); ++i) decide(*ps, reqs[i], sjs[i], T, t, segs[i]);
-            L = layout_for(*ps, segs, reqs.size());
-            if (L.total <= ws_bytes || !T) break;
-            T *= 2;
-            if (T > (1ull << 40)) T = 0;
-        }
-        if (L.total > ws_bytes)
-            return fail(MTGP_EINVAL, "workspace of %zu bytes too small (need %zu)", ws_bytes,
-                        L.total);
-        // polynomials: only streams whose cache lacks them (a thread per
-        // stream costs more than a batch of cached lookups)
-        std::vector<Seg *> split;
-        for (Seg &g : segs)
-            if (g.C > 1 && !g_ready(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1)))
-                split.push_back(&g);
-        parallel_for((int)split.size(), [&](int i) {
-            const Seg &g = *split[i];
-            ensure_g(*g.sj, g.lseg, (int)(g.c0 + (uint64_t)g.C - 1));
-        });
-
-        // build the uploaded image [0, up_end) in the pinned staging buffer:
-        // a zeroed header (claim counters, error count, stamps), the item
-        // tables, countdowns, polynomials (every byte that is read is
-        // written; the alignment gaps between tables are never read)
-        uint8_t *img = nullptr;
-        if (int rc = stage_acquire(stage, L.up_end, &img)) return rc;
-        std::memset(img, 0, 256);
-        auto at = [&](size_t off) { return img + off; };
-        std::vector<std::pair<uint64_t, BatchItem>> A, C;
-        std::vector<JumpItem> B;
-        size_t raw_off = L.off_raw, js_off = L.off_js, poly_off = L.off_poly;
-        for (size_t i = 0; i < reqs.size(); ++i) {
-            const Request &r = reqs[i];
-            const Seg &g = segs[i];
-            const uint32_t mode = r.dtype == MTGP_F32 ? MODE_F32 : 0u;
-            uint32_t *row = d_states + (size_t)r.stream * stride;
-            const uint64_t so = step_outputs(*ps, r.stream, t);
-            uint32_t *cd = (uint32_t *)(ws + L.off_cd) + i;
-            auto base_item = [&](uint64_t count, uint64_t out_off) {
-                BatchItem b;
-                std::memset(&b, 0, sizeof b);
-                b.stream = (uint32_t)r.stream;
-                b.mode = mode;
-                b.count = count;
-                b.out = (uint64_t)(uintptr_t)((char *)r.d_out + out_off * 4);
-                b.flag = r.flag;
-                b.countdown = r.flag ? (uint64_t)(uintptr_t)cd : 0;
-                return b;
-            };
-            if (g.C <= 1) {
-                BatchItem b = base_item(r.count, 0);
-                b.state_in = b.state_out = (uint64_t)(uintptr_t)row;
-                C.emplace_back((r.count + so - 1) / so, b);
-                ((uint32_t *)at(L.off_cd))[i] = 1;
-                continue;
-            }
-            const int D = g.sj->D;
-            const uint64_t P = (uint64_t)D + 1;
-            uint32_t *raw = (uint32_t *)(ws + raw_off);
-            raw_off += ((size_t)N + (size_t)D + 1 + 63) / 64 * 64 * 4;
-            uint32_t *js = (uint32_t *)(ws + js_off);  // C states of N words
-            js_off += (size_t)g.C * N * 4;
-            // A: prefix
-            BatchItem a = base_item(P, 0);
-            a.mode |= MODE_RAW;
-            a.state_in = (uint64_t)(uintptr_t)row;
-            a.state_out = (uint64_t)(uintptr_t)js;
-            a.raw = (uint64_t)(uintptr_t)raw;
-            a.flag = a.countdown = 0;
-            A.emplace_back((P + so - 1) / so, a);
-            // B: jumps, segment k >= 1 starts at output (c0+k-1)*lseg and
-            // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words
-            const size_t pw = ((size_t)D + 31) / 32;
-            for (int k = 1; k < g.C; ++k) {
-                const uint64_t c = g.c0 + (uint64_t)k - 1;
-                JumpItem j;
-                j.raw = (uint64_t)(uintptr_t)raw;
-                j.poly = (uint64_t)(uintptr_t)(ws + poly_off);
-                j.out = (uint64_t)(uintptr_t)(js + (size_t)k * N);
-                j.nbits = (uint32_t)D;
-                j.m = (uint32_t)N;
-                std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
-                poly_off += pw * 4;
-                B.push_back(j);
-            }
-            while (B.size() % JUMP_BLOCK) {  // pad this stream's block
-                JumpItem z;
-                std::memset(&z, 0, sizeof z);
-                B.push_back(z);
-            }
-            // C: segments
-            for (int k = 0; k < g.C; ++k) {
-                const uint64_t c = k == 0 ? 0 : g.c0 + (uint64_t)k - 1;
-                const uint64_t start = k == 0 ? P : c * g.lseg;
-                const uint64_t end = std::min<uint64_t>(r.count, k == 0 ? g.c0 * g.lseg
-                                                                        : (c + 1) * g.lseg);
-                BatchItem b = base_item(end - start, start);
-                b.state_in = (uint64_t)(uintptr_t)(js + (size_t)k * N);
-                if (k + 1 < g.C) {
-                    b.mode |= MODE_VERIFY;
-                    b.verify = (uint64_t)(uintptr_t)(js + (size_t)(k + 1) * N);
-                } else {
-                    b.state_out = (uint64_t)(uintptr_t)row;
+        std::lock_guard<std::mutex> lk(ps->jump_mu);
+        if (ps->dirty.size() == (size_t)ps->n)
+            for (const Request &r : reqs)
+                if (ps->dirty[(size_t)r.stream]) {
+                    dirty = true;
+                    break;
                 }
-                C.emplace_back((end - start + so - 1) / so, b);
-            }
-            ((uint32_t *)at(L.off_cd))[i] = (uint32_t)g.C;
-        }
-        auto lpt = [](const auto &x, const auto &y) { return x.first > y.first; };
-        std::stable_sort(A.begin(), A.end(), lpt);
-        std::stable_sort(C.begin(), C.end(), lpt);
-        for (size_t i = 0; i < A.size(); ++i)
-            std::memcpy(at(L.off_A) + i * sizeof(BatchItem), &A[i].second, sizeof(BatchItem));
-        if (!B.empty()) std::memcpy(at(L.off_B), B.data(), B.size() * sizeof(JumpItem));
-        for (size_t i = 0; i < C.size(); ++i)
-            std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].second, sizeof(BatchItem));
-        nA = (uint32_t)A.size();
-        nB = (uint32_t)B.size();
-        nC = (uint32_t)C.size();
-        int rc = stage_commit(stage, L.up_end, ws, s);
+    }
+    if (w.sig == sig && !dirty && w.ps.lock() == ps) {
+        // same plan: the polynomials are in place; the item tables and
+        // request records (device pointers, countdowns) go up every call
+        int rc = stage_copy(w.stage, HDR_BYTES, w.tables_end, ws, s);
         if (rc) return rc;
-        std::lock_guard<std::mutex> lk(g_ws_mu);
-        g_ws[d_ws] = WsRecord{has_flags ? 0 : sig, nA, nB, nC};
     } else {
-        L = layout_for(*ps, std::vector<Seg>(), 0);  // only the fixed offsets are used below
-        // recover the item-table offsets from the recorded counts
-        L.off_A = 256;
-        L.off_B = L.off_A + al256((size_t)nA * sizeof(BatchItem));
-        L.off_C = L.off_B + al256((size_t)nB * sizeof(JumpItem));
+        w.sig = 0;
+        int rc = build_plan(ps, d_params, d_states, stride, reqs, ws, ws_bytes, s, t, w);
+        if (rc) return rc;
+        rc = stage_copy(w.stage, HDR_BYTES, w.up_end, ws, s);
+        if (rc) return rc;
+        w.sig = sig;
     }
 
     const bool stamps = g_stamps.load();
     if (!use_graph || !graphs_enabled())
-        return launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, s, stamps);
+        return launch_phases(*ps, d_params, ws, w, t, s, stamps, per_call_errors);
 
     int dev = 0;
     (void)hipGetDevice(&dev);
-    GraphKey key{d_ws, nA, nB, nC, d_params, ps->N, t.threads_per_stream, t.outputs_per_lane,
-                 t.workgroup_size, t.window_below_w, dev, stamps};
+    GraphKey key{d_ws, w.nA, w.nB, w.nC, d_params, ps->N, t.threads_per_stream,
+                 t.outputs_per_lane, t.workgroup_size, t.window_below_w, dev, stamps,
+                 per_call_errors};
     std::lock_guard<std::mutex> lk(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
         hipStream_t cs;
         auto cit = g_capture_streams.find(dev);
         if (cit == g_capture_streams.end()) {
-            hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+            e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
             if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
             g_capture_streams[dev] = cs;
         } else {
@@ -746,9 +900,9 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
             for (auto &kv : g_graphs) (void)hipGraphExecDestroy(kv.second);
             g_graphs.clear();
         }
-        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        int rc = launch_phases(*ps, d_params, ws, nA, nB, nC, L, t, cs, stamps);
+        int rc = launch_phases(*ps, d_params, ws, w, t, cs, stamps, per_call_errors);
         hipGraph_t gr = nullptr;
         e = hipStreamEndCapture(cs, &gr);
         if (rc) {
@@ -762,7 +916,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
         it = g_graphs.emplace(key, ge).first;
     }
-    hipError_t e = hipGraphLaunch(it->second, s);
+    e = hipGraphLaunch(it->second, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return MTGP_OK;
 }
@@ -796,12 +950,10 @@ static std::vector<Request> to_requests(const mtgp_work *items, int n) {
     return r;
 }
 
-static Staging g_stage;
-
 static int batch_common(const void *d_params, uint32_t *d_states, int stride,
                         const mtgp_work *h_items, int n_items, void *d_ws, size_t ws_bytes,
                         hipStream_t s, const mtgp_tuning *force, bool use_graph,
-                        Staging &stage) {
+                        WsState *own) {
     auto ps = lookup_params(d_params, 0);
     if (!ps) return MTGP_EINVAL;
     if (!d_states || stride < ps->N)
@@ -814,9 +966,11 @@ static int batch_common(const void *d_params, uint32_t *d_states, int stride,
         return fail(MTGP_EINVAL, "workspace of %zu bytes below the minimum %zu", ws_bytes,
                     batch_min_ws_bytes(n_items));
     const mtgp_tuning t = force ? *force : tuning_for(ps->N);
-    std::lock_guard<std::mutex> lk(stage.mu);
+    std::shared_ptr<WsState> held = own ? nullptr : ws_state(d_ws, true);
+    WsState &w = own ? *own : *held;
+    std::lock_guard<std::mutex> lk(w.mu);
     return run_batch(ps, d_params, d_states, stride, to_requests(h_items, n_items), d_ws,
-                     ws_bytes, s, t, use_graph, stage);
+                     ws_bytes, s, t, use_graph, w, false);
 }
 
 }  // namespace mtgp
@@ -839,7 +993,7 @@ int mtgp_stream_polynomials(const void *d_params, int n_streams, uint32_t *h_coe
         return fail(MTGP_EINVAL, "words_per_stream %d < %d", words_per_stream, need);
     std::vector<int> all((size_t)n_streams);
     for (int k = 0; k < n_streams; ++k) all[(size_t)k] = k;
-    int rc = ensure_jumps(ps, d_params, all, tuning_for(ps->N), (hipStream_t)stream);
+    int rc = ensure_jumps(ps, d_params, nullptr, 0, all, tuning_for(ps->N), (hipStream_t)stream);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(ps->jump_mu);
     for (int k = 0; k < n_streams; ++k) {
@@ -871,20 +1025,29 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items, i
     for (const Request &r : reqs)
         if (wants_split(*ps, r, T, t)) want.push_back(r.stream);
     if (!want.empty()) {
-        rc = ensure_jumps(ps, d_params, want, t, nullptr);
+        rc = ensure_jumps(ps, d_params, nullptr, 0, want, t, nullptr);
         if (rc) return rc;
     }
     std::vector<Seg> segs(reqs.size());
-    for (size_t i = 0; i < reqs.size(); ++i) {
-        StreamJump *sj = nullptr;
-        {
-            std::lock_guard<std::mutex> lk(ps->jump_mu);
-            if (ps->jumps.size() == (size_t)ps->n) sj = ps->jumps[reqs[i].stream].get();
+    {
+        std::lock_guard<std::mutex> lk(ps->jump_mu);
+        size_tracking(*ps);
+        for (size_t i = 0; i < reqs.size(); ++i) {
+            const int k = reqs[i].stream;
+            const StreamJump *sj = ps->jumps[(size_t)k].get();
+            segs[i].req = (int)i;
+            if (sj && sj->status == 1 && !ps->dirty[(size_t)k]) {
+                decide(*ps, reqs[i], sj->D, T, t, segs[i]);
+            } else if (!sj || ps->dirty[(size_t)k]) {
+                // the polynomial will be built from the stream's state at
+                // generation time: size for the most segments (D = 1) and
+                // the largest degree (mexp)
+                decide(*ps, reqs[i], 1, T, t, segs[i]);
+                if (segs[i].C > 1) segs[i].Dsize = (int)ps->mexp;
+            }
         }
-        segs[i].req = (int)i;
-        decide(*ps, reqs[i], sj, T, t, segs[i]);
     }
-    *bytes = std::max(layout_for(*ps, segs, reqs.size()).total, batch_min_ws_bytes(n_items));
+    *bytes = std::max(layout_for(*ps, segs).total, batch_min_ws_bytes(n_items));
     return MTGP_OK;
 }
 
@@ -892,7 +1055,7 @@ int mtgp_generate_batch(const void *d_params, uint32_t *d_states, int state_stri
                         const mtgp_work *h_items, int n_items, void *d_workspace,
                         size_t workspace_bytes, void *stream) {
     return batch_common(d_params, d_states, state_stride, h_items, n_items, d_workspace,
-                        workspace_bytes, (hipStream_t)stream, nullptr, true, g_stage);
+                        workspace_bytes, (hipStream_t)stream, nullptr, true, nullptr);
 }
 
 int mtgp_set_phase_timing(int enable) {
@@ -921,15 +1084,28 @@ int mtgp_batch_phase_times(void *d_workspace, void *stream, double *h_us) {
 int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n) {
     if (!d_workspace || !n) return fail(MTGP_EINVAL, "NULL workspace or n");
     hipStream_t s = (hipStream_t)stream;
-    uint32_t v = 0;
-    hipError_t e = hipMemcpyAsync(&v, (uint32_t *)d_workspace + 2, 4, hipMemcpyDeviceToHost, s);
+    uint32_t v[HDR_TAG + 2 - HDR_ERR] = {};
+    uint32_t *hw = (uint32_t *)d_workspace + HDR_ERR;
+    hipError_t e = hipMemcpyAsync(v, hw, sizeof v, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = launch_clear(hw, HDR_ERR_WORDS, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "read error count");
-    *n = v;
-    const uint32_t zero = 0;
-    e = hipMemcpyAsync((uint32_t *)d_workspace + 2, &zero, 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    return e == hipSuccess ? MTGP_OK : hip_fail(e, "reset error count");
+    if (e != hipSuccess) return hip_fail(e, "read and reset the repair count");
+    // a header without this workspace's tag holds no count of ours
+    const uint64_t tag = header_tag(d_workspace);
+    const bool ours = v[HDR_TAG - HDR_ERR] == (uint32_t)tag &&
+                      v[HDR_TAG + 1 - HDR_ERR] == (uint32_t)(tag >> 32);
+    *n = ours ? v[0] : 0u;
+    if (*n != 0) {
+        // rebuild the logged streams' polynomials from their current states
+        // and re-upload the whole plan next time (the cached polynomials
+        // in the workspace may have been overwritten)
+        if (auto w = ws_state(d_workspace, false)) {
+            std::lock_guard<std::mutex> lk(w->mu);
+            if (auto ps = w->ps.lock()) note_repairs(*ps, v, w->split_streams);
+            w->sig = 0;
+        }
+    }
+    return MTGP_OK;
 }
 
 int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stride,
@@ -960,16 +1136,16 @@ int mtgp_autotune(const void *d_params, const uint32_t *d_states, int state_stri
         (void)hipEventDestroy(ev0);
         return hip_fail(e, "hipEventCreate");
     }
-    Staging stage;
+    WsState wst;  // the scratch workspace's own plan state
     auto time_one = [&](const mtgp_tuning &t, float *ms) -> int {
         int rc = batch_common(d_params, scratch_states, state_stride, h_items, n_items, ws,
-                              ws_bytes, s, &t, false, stage);  // warm-up + planning
+                              ws_bytes, s, &t, false, &wst);  // warm-up + planning
         if (rc) return rc;
         float total = 0.f;
         for (int r = 0; r < reps; ++r) {
             (void)hipEventRecord(ev0, s);
             rc = batch_common(d_params, scratch_states, state_stride, h_items, n_items, ws,
-                              ws_bytes, s, &t, false, stage);
+                              ws_bytes, s, &t, false, &wst);
             (void)hipEventRecord(ev1, s);
             if (rc) return rc;
             hipError_t e2 = hipEventSynchronize(ev1);

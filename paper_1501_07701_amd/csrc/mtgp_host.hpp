@@ -24,18 +24,46 @@ struct ParamSet {
     std::vector<uint32_t> W;   // step width N - pos per stream
     std::vector<uint8_t> lin;  // 1 where rec_tbl is linear (the windowed path applies)
     uint64_t generation = 0;   // changes whenever the parameter block is rewritten
+    // Jump-ahead data per stream (guarded by jump_mu).  A stream's
+    // polynomial annihilates the orbits it was built from; `seeded` says
+    // whether the stream's state was last set from its seed status (so its
+    // orbit is the seed's), `dirty` that the state may lie outside every
+    // orbit the current polynomial was built from (after an import, a
+    // parameter reload, or an observed segment-check failure).
     std::mutex jump_mu;
     std::vector<std::shared_ptr<StreamJump>> jumps;  // per stream, or null
+    std::vector<uint8_t> seeded;
+    std::vector<uint8_t> dirty;
 };
 
-// Pinned staging buffer for uploads; reused once its last copy finished.
+// Marks streams [0, n) as seeded (mtgp_seed_states) or as holding states
+// from elsewhere (mtgp_state_import), for the jump-ahead planner.
+void note_states_seeded(ParamSet &ps, int n);
+void note_states_foreign(ParamSet &ps, const int32_t *streams, int n);
+
+// Pinned staging buffer for uploads; rewritten only once its last copy
+// finished.
 struct Staging {
-    std::mutex mu;
     uint8_t *host = nullptr;
     size_t cap = 0;
     hipEvent_t done = nullptr;
     bool pending = false;
     ~Staging();
+};
+
+// What the library keeps for one batch workspace: the pinned image of the
+// last plan and where its parts lie.  Every call uploads the plan's item
+// tables and request records (so a workspace whose memory was reused in
+// between is rewritten before any kernel reads it); the jump polynomials
+// are uploaded when the plan changes.  The caller holds `mu` for a call.
+struct WsState {
+    std::mutex mu;
+    Staging stage;
+    uint64_t sig = 0;          // plan signature, 0 = no plan
+    uint32_t nA = 0, nB = 0, nC = 0, nF = 0;  // prefix, jump, segment, check items
+    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, tables_end = 0, up_end = 0;
+    std::weak_ptr<ParamSet> ps;         // parameter set of the last plan
+    std::vector<int32_t> split_streams;  // streams the last plan split
 };
 
 int fail(int code, const char *fmt, ...);
@@ -59,10 +87,17 @@ struct Request {
 };
 
 // Plans, uploads and launches one batch.  Splits long streams into
-// jump-ahead segments as far as ws_bytes allows.  The caller holds stage.mu.
+// jump-ahead segments as far as ws_bytes allows.  The caller holds wst.mu.
+// per_call_errors zeroes the workspace's repair count and log at the start
+// of the call (else they accumulate until mtgp_batch_errors reads them).
 int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
               int stride, const std::vector<Request> &reqs, void *d_ws, size_t ws_bytes,
-              hipStream_t s, const mtgp_tuning &t, bool use_graph, Staging &stage);
+              hipStream_t s, const mtgp_tuning &t, bool use_graph, WsState &wst,
+              bool per_call_errors);
+// Streams named in a workspace header's repair log (all streams the plan
+// split when the log overflowed) are marked dirty so that their jump-ahead
+// polynomial is rebuilt from their current state.
+void note_repairs(ParamSet &ps, const uint32_t *err_words, const std::vector<int32_t> &split);
 size_t batch_min_ws_bytes(int n_items);
 int validate_requests(const ParamSet &ps, const mtgp_work *items, int n);
 

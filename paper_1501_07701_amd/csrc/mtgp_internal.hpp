@@ -38,8 +38,29 @@ constexpr int WIN_MAT_WORDS = 128;   // 8 nibbles x 16 entries
 enum : uint32_t {
     MODE_F32 = 1u,     // float32 output (else uint32)
     MODE_RAW = 2u,     // also store the raw words x_0 .. x_{N+count-1} at raw
-    MODE_VERIFY = 4u,  // compare the end state with verify[0..N), count mismatches
+    MODE_VERIFY = 4u,  // compare the end state with verify[0..N); a mismatch
+                       // marks the item's request record as failed
+    MODE_FIXUP = 8u,   // request check (last launch of a batch): regenerate
+                       // the request from its record if a segment failed,
+                       // then raise `flag`
 };
+
+// Request record (64 bytes) of a request split by jump-ahead: its segments
+// mark `failed` when a check fails, and the batch's last launch (after
+// every segment has finished, so no later store can land on its outputs)
+// regenerates such a request in order from `orig`.
+struct ReqRec {
+    uint32_t failed;     // nonzero once a segment's end state missed the next start
+    uint32_t stream;
+    uint32_t mode;       // MODE_F32 or 0
+    uint32_t reserved0;
+    uint64_t count;      // outputs of the whole request
+    uint64_t out;        // device address of its first output
+    uint64_t orig;       // N words: the stream's state when the request starts
+    uint64_t row;        // where the request's final state goes
+    uint64_t reserved[2];
+};
+static_assert(sizeof(ReqRec) == 64, "ReqRec layout");
 
 // Device work-list entry (80 bytes): advance a stream from state_in by
 // `count` outputs written to `out`, store the end state at state_out.
@@ -52,12 +73,30 @@ struct BatchItem {
     uint64_t state_out;  // N words, or 0
     uint64_t raw;        // MODE_RAW destination
     uint64_t verify;     // MODE_VERIFY reference state
+    uint64_t rec;        // the request's ReqRec (MODE_VERIFY, MODE_FIXUP), or 0
     uint64_t flag;       // 0, or a host-mapped uint32 set to 1 when the request is done
-    uint64_t countdown;  // 0, or a device uint32 of segments still running for
-                         // this request: the segment that ends it raises `flag`
     uint64_t reserved;
 };
 static_assert(sizeof(BatchItem) == 80, "BatchItem layout");
+
+// Batch workspace header (256 bytes, never part of an uploaded plan):
+//   word 0, 1   claim counters of the prefix and segment launches
+//   word 2      requests regenerated after a failed segment check
+//   word 3      entries written to the log (may exceed HDR_LOG_MAX)
+//   word 4..11  stream ids of the first HDR_LOG_MAX such requests
+//   word 12     claim counter of the request-check launch
+//   word 13, 14 tag: a 64-bit value derived from the workspace address; a
+//               header without it (fresh or reused memory) is cleared by
+//               the first launch of the next call
+//   byte 64..95 phase timestamps (64-bit: start, after the prefix items,
+//               after the jump-ahead evaluation, end)
+constexpr int HDR_ERR = 2;
+constexpr int HDR_LOG_MAX = 8;
+constexpr int HDR_ERR_WORDS = 2 + HDR_LOG_MAX;  // words HDR_ERR .. HDR_ERR + 9
+constexpr int HDR_FIX_CLAIM = 12;
+constexpr int HDR_TAG = 13;
+constexpr size_t HDR_STAMP_BYTE = 64;
+constexpr size_t HDR_BYTES = 256;
 
 // Jump evaluation item (32 bytes): out[m] = XOR_{i < nbits, g_i = 1}
 // raw[1 + i + m] for m < m_count.
@@ -84,7 +123,7 @@ struct LaunchArgs {
     uint64_t plain_count;
     uint32_t plain_mode;
     uint32_t *counter;
-    uint32_t *err;
+    uint32_t *err;           // header word HDR_ERR (repair count, then the log)
     uint32_t win_below;      // window path for eligible streams with W below this
     bool persistent;
     int num_cus;
@@ -104,10 +143,13 @@ int variant_slots_per_cu(int n_words, int tps, int k, int wpb);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s);
 hipError_t launch_reset(uint32_t *counter, hipStream_t s);
-// Batch workspace header: claim counters (words 0, 1), segment-check errors
-// (word 2), phase timestamps (64-bit words from byte HDR_STAMP_BYTE: start,
-// after the prefix items, after the jumps, end).
-constexpr size_t HDR_STAMP_BYTE = 64;
+// Zeroes n consecutive words with a small kernel (no memset node, so it is
+// safe inside captured graphs).
+hipError_t launch_clear(uint32_t *p, uint32_t n, hipStream_t s);
+// First launch of every batch call: zeroes the claim counters; zeroes the
+// repair count and log when clear_errors is set or the header lacks `tag`
+// (then also the timestamps), and writes the tag.
+hipError_t launch_header(uint32_t *hdr, uint64_t tag, bool clear_errors, hipStream_t s);
 hipError_t launch_stamp(uint64_t *dst, hipStream_t s);
 hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t stride,
                             uint32_t n_streams, uint64_t count, uint32_t *out, uint32_t f32,

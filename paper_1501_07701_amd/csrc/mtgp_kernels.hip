@@ -422,12 +422,13 @@ struct Core {
         }
     }
 
-    // Advance one stream by item.count outputs.
+    // Advance one stream by item.count outputs.  A MODE_VERIFY item that
+    // ends in a state other than item.verify sets *fail.
     template <bool F32>
     static __device__ __forceinline__ void run(const uint32_t *__restrict__ prm,
                                                const BatchItem &item,
                                                uint32_t *__restrict__ buf, uint32_t lane,
-                                               uint32_t *__restrict__ err, uint32_t win_below) {
+                                               uint32_t *fail, uint32_t win_below) {
         // a stream takes the window path when the host gave it window data
         const bool win = TPS == 64 && prm[P_WIN_E] != 0u && prm[P_W] < win_below;
         uint32_t *__restrict__ tbl = buf + (win ? WBUF : BUF);
@@ -476,12 +477,12 @@ struct Core {
         group_sync<TPS>();
         if (st_out != nullptr)
             for (uint32_t i = lane; i < N; i += TPS) st_out[i] = buf[h - N + i];
-        if (item.mode & MODE_VERIFY) {
+        if ((item.mode & MODE_VERIFY) && fail != nullptr) {
             // the end state must equal the next segment's jumped start state
             const uint32_t *ref = reinterpret_cast<const uint32_t *>(item.verify);
             uint32_t bad = 0;
             for (uint32_t i = lane; i < N; i += TPS) bad |= (buf[h - N + i] != ref[i]) ? 1u : 0u;
-            if (bad) atomicAdd(err, 1u);
+            if (bad) atomicOr(fail, 1u);
         }
     }
 };
@@ -495,6 +496,25 @@ struct PlainArgs {
     uint32_t *out;
     uint64_t count;
 };
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Value of lane 0 (wave) or thread 0 (workgroup) for the whole group.
+template <int TPS>
+__device__ __forceinline__ uint32_t group_first(uint32_t v, uint32_t *slot) {
+    if constexpr (TPS == 64) {
+        return __builtin_amdgcn_readfirstlane(v);
+    } else {
+        __syncthreads();
+        if (threadIdx.x == 0) *slot = v;
+        __syncthreads();
+        return *slot;
+    }
+}
 
 template <int N, int TPS, int K, int WPB>
 __global__ void __launch_bounds__(TPS == 64 ? 64 * WPB : TPS)
@@ -513,16 +533,9 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
 
     while (true) {
         if (persistent) {
-            if constexpr (TPS == 64) {
-                uint32_t v = 0;
-                if (lane == 0) v = atomicAdd(counter, 1u);
-                it = __builtin_amdgcn_readfirstlane(v);
-            } else {
-                __syncthreads();
-                if (threadIdx.x == 0) s_claim = atomicAdd(counter, 1u);
-                __syncthreads();
-                it = s_claim;
-            }
+            uint32_t v = 0;
+            if (lane == 0) v = atomicAdd(counter, 1u);
+            it = group_first<TPS>(v, &s_claim);
         }
         if (it >= n_items) break;
         BatchItem item;
@@ -535,31 +548,52 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
             item.count = plain.count;
             item.out = (uint64_t)(uintptr_t)(plain.out + (uint64_t)it * plain.count);
             item.state_in = item.state_out = (uint64_t)(uintptr_t)row;
-            item.raw = item.verify = item.flag = item.countdown = 0;
+            item.raw = item.verify = item.rec = item.flag = 0;
         }
-        const uint32_t *prm = params + (uint64_t)item.stream * P_WORDS;
+        if (item.mode & MODE_FIXUP) {
+            // Request check, after every segment of the request has
+            // finished: if a segment started from a wrong jumped state (the
+            // stream's state lay outside the orbit its polynomial
+            // annihilates), regenerate the whole request in order from its
+            // start state and log it.  Record fields are loaded from
+            // writable memory, so they are made wave-uniform explicitly.
+            const ReqRec *rec = reinterpret_cast<const ReqRec *>(item.rec);
+            const uint32_t failed = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&rec->failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            item.count = 0;
+            if (failed) {
+                item.stream = __builtin_amdgcn_readfirstlane(rec->stream);
+                item.mode = __builtin_amdgcn_readfirstlane(rec->mode);
+                item.count = uniform64(rec->count);
+                item.out = uniform64(rec->out);
+                item.state_in = uniform64(rec->orig);
+                item.state_out = uniform64(rec->row);
+                item.raw = item.verify = 0;
+                if (lane == 0) {
+                    atomicAdd(err, 1u);
+                    const uint32_t slot = atomicAdd(err + 1, 1u);
+                    if (slot < (uint32_t)HDR_LOG_MAX) err[2 + slot] = item.stream;
+                }
+            }
+        }
         if (item.count > 0) {
+            const uint32_t *prm = params + (uint64_t)item.stream * P_WORDS;
+            uint32_t *fail = (item.mode & MODE_VERIFY)
+                                 ? &reinterpret_cast<ReqRec *>(item.rec)->failed
+                                 : nullptr;
             if (item.mode & MODE_F32)
-                C::template run<true>(prm, item, buf, lane, err, win_below);
+                C::template run<true>(prm, item, buf, lane, fail, win_below);
             else
-                C::template run<false>(prm, item, buf, lane, err, win_below);
+                C::template run<false>(prm, item, buf, lane, fail, win_below);
         }
         if (item.flag != 0) {
-            // Publish completion of the request to the host once its last
-            // segment is done: every lane's output and state stores are made
-            // visible system-wide first.
+            // Publish completion of the request to the host: every lane's
+            // output and state stores are made visible system-wide first.
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
             group_sync<TPS>();
-            if (lane == 0) {
-                bool last = true;
-                if (item.countdown != 0)
-                    last = __hip_atomic_fetch_add(reinterpret_cast<uint32_t *>(item.countdown),
-                                                  0xFFFFFFFFu, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT) == 1u;
-                if (last)
-                    __hip_atomic_store(reinterpret_cast<uint32_t *>(item.flag), 1u,
-                                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            }
+            if (lane == 0)
+                __hip_atomic_store(reinterpret_cast<uint32_t *>(item.flag), 1u, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_SYSTEM);
         }
         if (!persistent) it += n_groups;
     }
@@ -703,6 +737,25 @@ __global__ void seed_kernel(const uint32_t *__restrict__ params,
 }
 
 __global__ void reset_counter_kernel(uint32_t *counter) { *counter = 0u; }
+
+__global__ void clear_kernel(uint32_t *p, uint32_t n) {
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+// One wave; lane i owns header word i (i < 24).  Every lane reads the tag
+// before any lane writes it.
+__global__ void header_kernel(uint32_t *hdr, uint32_t tag_lo, uint32_t tag_hi,
+                              uint32_t clear_errors) {
+    const uint32_t i = threadIdx.x;
+    const bool fresh = hdr[HDR_TAG] != tag_lo || hdr[HDR_TAG + 1] != tag_hi;
+    __builtin_amdgcn_wave_barrier();
+    const bool claim = i < (uint32_t)HDR_ERR || i == (uint32_t)HDR_FIX_CLAIM;
+    const bool errw = i >= (uint32_t)HDR_ERR && i < (uint32_t)(HDR_ERR + HDR_ERR_WORDS);
+    const bool stamp = i >= HDR_STAMP_BYTE / 4 && i < HDR_STAMP_BYTE / 4 + 8;
+    if (claim || (errw && (fresh || clear_errors)) || (stamp && fresh)) hdr[i] = 0u;
+    if (i == (uint32_t)HDR_TAG) hdr[i] = tag_lo;
+    if (i == (uint32_t)HDR_TAG + 1) hdr[i] = tag_hi;
+}
 
 // Device timestamp (the constant-rate wall clock) for phase timing.
 __global__ void stamp_kernel(uint64_t *dst) {
@@ -871,6 +924,20 @@ hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride
 hipError_t launch_reset(uint32_t *counter, hipStream_t s) {
     (void)hipGetLastError();  // report this launch only
     hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear(uint32_t *p, uint32_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(clear_kernel, dim3(1), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_header(uint32_t *hdr, uint64_t tag, bool clear_errors, hipStream_t s) {
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(header_kernel, dim3(1), dim3(64), 0, s, hdr, (uint32_t)tag,
+                       (uint32_t)(tag >> 32), clear_errors ? 1u : 0u);
     return hipGetLastError();
 }
 

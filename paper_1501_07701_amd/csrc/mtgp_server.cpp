@@ -106,7 +106,8 @@ struct Slot {
     hipEvent_t done = nullptr;
     void *d_ws = nullptr;          // work list + counter, carved from the pool
     uint32_t *flags = nullptr;     // pinned, host-mapped, one per item
-    std::unique_ptr<Staging> stage;
+    uint32_t *h_err = nullptr;     // pinned: the batch's repair count and log
+    std::unique_ptr<WsState> wst;
     bool busy = false;
     std::vector<std::vector<uint64_t>> item_tickets;  // tickets fused into each item
     std::vector<uint8_t> item_done;
@@ -142,6 +143,8 @@ struct Server {
     std::unique_ptr<Pool> pool;
     uint64_t next_ticket = 1;
     size_t queued = 0;
+    uint64_t repaired = 0;  // requests regenerated after a failed segment check
+    int waiters = 0;        // threads inside mtgp_wait (destroy waits for them)
     bool stop = false;
     std::vector<Slot> slots;
     std::thread thr;
@@ -246,15 +249,19 @@ struct Server {
         int rc;
         lk.unlock();
         {
-            std::lock_guard<std::mutex> sg(sl.stage->mu);
+            std::lock_guard<std::mutex> sg(sl.wst->mu);
             rc = run_batch(ps, d_params, d_states, stride, work, sl.d_ws, ws_bytes, sl.hs,
-                           tuning_for(ps->N), false, *sl.stage);
+                           tuning_for(ps->N), false, *sl.wst, true);
+            if (rc == MTGP_OK) {
+                // the batch's repair count and log come back with the slot
+                hipError_t e = hipMemcpyAsync(sl.h_err, (uint32_t *)sl.d_ws + HDR_ERR,
+                                              HDR_ERR_WORDS * sizeof(uint32_t),
+                                              hipMemcpyDeviceToHost, sl.hs);
+                if (e == hipSuccess) e = hipEventRecord(sl.done, sl.hs);
+                if (e != hipSuccess) rc = hip_fail(e, "slot completion record");
+            }
         }
         lk.lock();
-        if (rc == MTGP_OK) {
-            hipError_t e = hipEventRecord(sl.done, sl.hs);
-            if (e != hipSuccess) rc = hip_fail(e, "hipEventRecord(slot)");
-        }
         if (rc != MTGP_OK) {
             for (auto &g : sl.item_tickets)
                 for (uint64_t tk : g) finish_locked(reqs[tk], R_FAILED);
@@ -290,6 +297,12 @@ struct Server {
             if (sl.n_done == sl.n_items) {
                 hipError_t e = hipEventQuery(sl.done);
                 if (e == hipSuccess) {
+                    if (sl.h_err[0] != 0) {
+                        // results are exact (the device regenerated them);
+                        // rebuild those streams' polynomials from their states
+                        repaired += sl.h_err[0];
+                        note_repairs(*ps, sl.h_err, sl.wst->split_streams);
+                    }
                     sl.busy = false;
                     any = true;
                 } else if (e != hipErrorNotReady) {
@@ -419,13 +432,17 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states, int state_strid
     int rc = MTGP_OK;
     for (int i = 0; i < o.max_inflight_batches && rc == MTGP_OK; ++i) {
         Slot &sl = S.slots[i];
-        sl.stage = std::make_unique<Staging>();
+        sl.wst = std::make_unique<WsState>();
         sl.d_ws = (char *)d_pool + (size_t)i * ws;
         hipError_t e = hipStreamCreateWithFlags(&sl.hs, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess)
             e = hipHostMalloc((void **)&sl.flags, sizeof(uint32_t) * (size_t)o.max_batch_items,
                               hipHostMallocMapped | hipHostMallocCoherent);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&sl.h_err, sizeof(uint32_t) * HDR_ERR_WORDS,
+                              hipHostMallocDefault);
+        if (e == hipSuccess) std::memset(sl.h_err, 0, sizeof(uint32_t) * HDR_ERR_WORDS);
         if (e != hipSuccess) rc = hip_fail(e, "server slot setup");
     }
     S.d_pool = (char *)d_pool + reserved;
@@ -434,6 +451,7 @@ int mtgp_server_create(const void *d_params, uint32_t *d_states, int state_strid
     if (rc != MTGP_OK) {
         for (Slot &sl : S.slots) {
             if (sl.flags) (void)hipHostFree(sl.flags);
+            if (sl.h_err) (void)hipHostFree(sl.h_err);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.hs) (void)hipStreamDestroy(sl.hs);
         }
@@ -543,7 +561,7 @@ int mtgp_poll(mtgp_server *srv, uint64_t ticket, int *state, const void **d_resu
 
 int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int32_t *stream_ids,
                        const uint64_t *counts, const int *dtypes, int n, uint64_t *h_latency_ns,
-                       uint64_t *h_stages_ns) {
+                       uint64_t *h_stages_ns, void *const *d_keep) {
     if (!srv || n < 0 || (n > 0 && (!t_arrival_ns || !stream_ids || !counts || !dtypes ||
                                     !h_latency_ns)))
         return fail(MTGP_EINVAL, "NULL argument or n=%d", n);
@@ -555,14 +573,28 @@ int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int
             (dtypes[i] != MTGP_U32 && dtypes[i] != MTGP_F32) || counts[i] * 4 > S.pool->size())
             return fail(MTGP_EINVAL, "request %d: bad stream, count or dtype", i);
     }
+    hipStream_t cs = nullptr;  // copies of kept results
+    if (d_keep) {
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreate(replay copies)");
+    }
+    struct Kept {
+        int i;
+        uint64_t ticket, off, bytes;
+    };
+    int rc = MTGP_OK;
     const uint64_t start = S.now();
     std::vector<uint64_t> tickets((size_t)n, 0);
     std::vector<int> open;  // submitted, not yet finished
     int next = 0, finished = 0;
-    while (finished < n) {
+    while (finished < n && rc == MTGP_OK) {
+        std::vector<Kept> kept;
         {
             std::unique_lock<std::mutex> lk(S.mu);
-            if (S.stop) return fail(MTGP_ECANCELED, "server is shutting down");
+            if (S.stop) {
+                rc = fail(MTGP_ECANCELED, "server is shutting down");
+                break;
+            }
             const uint64_t t = S.now();
             bool queued_any = false;
             while (next < n && start + t_arrival_ns[next] <= t &&
@@ -583,12 +615,16 @@ int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int
                 queued_any = true;
             }
             if (queued_any) S.cv_work.notify_one();
-            // collect what finished; its pool bytes go back at once
+            // collect what finished; its pool bytes go back at once (after
+            // the copy for kept results)
             size_t w = 0;
             for (size_t k = 0; k < open.size(); ++k) {
                 const int i = open[k];
                 auto it = S.reqs.find(tickets[(size_t)i]);
-                if (it == S.reqs.end()) return fail(MTGP_EDEVICE, "replayed request vanished");
+                if (it == S.reqs.end()) {
+                    rc = fail(MTGP_EDEVICE, "replayed request vanished");
+                    break;
+                }
                 Req &r = it->second;
                 if (r.state == R_DONE) {
                     h_latency_ns[i] = r.t_done - (start + t_arrival_ns[i]);
@@ -597,21 +633,55 @@ int mtgp_server_replay(mtgp_server *srv, const uint64_t *t_arrival_ns, const int
                         h_stages_ns[3 * (size_t)i + 1] = r.t_launch - r.t_admit;
                         h_stages_ns[3 * (size_t)i + 2] = r.t_done - r.t_launch;
                     }
+                    if (d_keep && d_keep[i]) {
+                        kept.push_back(Kept{i, r.ticket, r.off, r.bytes});
+                        continue;
+                    }
                     if (r.bytes) S.pool->release(r.off, r.bytes);
                     S.admit_dirty = true;
                     S.reqs.erase(it);
                     ++finished;
                     S.cv_work.notify_one();
                 } else if (r.state == R_FAILED || r.state == R_CANCELED) {
-                    return fail(MTGP_EDEVICE, "replayed request %d failed", i);
+                    rc = fail(MTGP_EDEVICE, "replayed request %d failed", i);
+                    break;
                 } else {
                     open[w++] = i;
                 }
             }
             open.resize(w);
         }
+        if (rc != MTGP_OK) break;
+        if (!kept.empty()) {
+            // outside the lock: the server keeps launching meanwhile
+            for (const Kept &kp : kept) {
+                hipError_t e = hipMemcpyAsync(d_keep[kp.i], S.d_pool + kp.off, kp.bytes,
+                                              hipMemcpyDeviceToDevice, cs);
+                if (e != hipSuccess) rc = hip_fail(e, "hipMemcpyAsync(kept result)");
+            }
+            hipError_t e = hipStreamSynchronize(cs);
+            if (e != hipSuccess && rc == MTGP_OK) rc = hip_fail(e, "hipStreamSynchronize(kept)");
+            std::lock_guard<std::mutex> lk(S.mu);
+            for (const Kept &kp : kept) {
+                if (kp.bytes) S.pool->release(kp.off, kp.bytes);
+                S.reqs.erase(kp.ticket);
+                ++finished;
+            }
+            S.admit_dirty = true;
+            S.cv_work.notify_one();
+            continue;
+        }
         std::this_thread::sleep_for(std::chrono::microseconds(10));
     }
+    if (cs) (void)hipStreamDestroy(cs);
+    return rc;
+}
+
+int mtgp_server_repaired(mtgp_server *srv, uint64_t *n) {
+    if (!srv || !n) return fail(MTGP_EINVAL, "NULL server or n");
+    Server &S = srv->s;
+    std::lock_guard<std::mutex> lk(S.mu);
+    *n = S.repaired;
     return MTGP_OK;
 }
 
@@ -619,6 +689,12 @@ int mtgp_wait(mtgp_server *srv, uint64_t ticket, uint64_t timeout_ns) {
     if (!srv) return fail(MTGP_EINVAL, "NULL server");
     Server &S = srv->s;
     std::unique_lock<std::mutex> lk(S.mu);
+    ++S.waiters;
+    auto leave = [&](int rc) {
+        --S.waiters;
+        S.cv_done.notify_all();  // mtgp_server_destroy may be waiting for us
+        return rc;
+    };
     auto done = [&] {
         auto it = S.reqs.find(ticket);
         return it == S.reqs.end() || it->second.state >= R_DONE;
@@ -626,14 +702,16 @@ int mtgp_wait(mtgp_server *srv, uint64_t ticket, uint64_t timeout_ns) {
     if (timeout_ns == 0) {
         S.cv_done.wait(lk, done);
     } else if (!S.cv_done.wait_for(lk, std::chrono::nanoseconds(timeout_ns), done)) {
-        return fail(MTGP_ETIMEDOUT, "ticket %llu not done after %llu ns",
-                    (unsigned long long)ticket, (unsigned long long)timeout_ns);
+        return leave(fail(MTGP_ETIMEDOUT, "ticket %llu not done after %llu ns",
+                          (unsigned long long)ticket, (unsigned long long)timeout_ns));
     }
     auto it = S.reqs.find(ticket);
-    if (it == S.reqs.end()) return fail(MTGP_ENOENT, "ticket %llu unknown", (unsigned long long)ticket);
-    if (it->second.state == R_CANCELED) return fail(MTGP_ECANCELED, "ticket cancelled");
-    if (it->second.state == R_FAILED) return fail(MTGP_EDEVICE, "request failed on the device");
-    return MTGP_OK;
+    if (it == S.reqs.end())
+        return leave(fail(MTGP_ENOENT, "ticket %llu unknown", (unsigned long long)ticket));
+    if (it->second.state == R_CANCELED) return leave(fail(MTGP_ECANCELED, "ticket cancelled"));
+    if (it->second.state == R_FAILED)
+        return leave(fail(MTGP_EDEVICE, "request failed on the device"));
+    return leave(MTGP_OK);
 }
 
 int mtgp_release(mtgp_server *srv, uint64_t ticket) {
@@ -684,9 +762,16 @@ int mtgp_server_destroy(mtgp_server *srv) {
     }
     S.cv_work.notify_all();
     if (S.thr.joinable()) S.thr.join();
+    {
+        // threads blocked in mtgp_wait have been woken (their requests are
+        // finished or cancelled): let them leave before the server goes
+        std::unique_lock<std::mutex> lk(S.mu);
+        S.cv_done.wait(lk, [&] { return S.waiters == 0; });
+    }
     int rc = MTGP_OK;
     for (Slot &sl : S.slots) {
         if (sl.flags) (void)hipHostFree(sl.flags);
+        if (sl.h_err) (void)hipHostFree(sl.h_err);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.hs) (void)hipStreamDestroy(sl.hs);
     }

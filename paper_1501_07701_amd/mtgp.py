@@ -102,7 +102,9 @@ _SIGS = {
                            ctypes.c_int),
     "mtgp_submit": ([_VP, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int, _U64P], ctypes.c_int),
     "mtgp_submit_many": ([_VP, _VP, _VP, _VP, ctypes.c_int, _VP], ctypes.c_int),
-    "mtgp_server_replay": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP], ctypes.c_int),
+    "mtgp_server_replay": ([_VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP, _VP],
+                           ctypes.c_int),
+    "mtgp_server_repaired": ([_VP, _U64P], ctypes.c_int),
     "mtgp_poll": ([_VP, ctypes.c_uint64, _INTP, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "mtgp_wait": ([_VP, ctypes.c_uint64, ctypes.c_uint64], ctypes.c_int),
     "mtgp_release": ([_VP, ctypes.c_uint64], ctypes.c_int),
@@ -459,9 +461,11 @@ class Server:
                                       int(st.shape[0]), tk.ctypes.data), "mtgp_submit_many")
         return tk
 
-    def replay(self, t_arrival_ns, stream_ids, counts, dtypes):
+    def replay(self, t_arrival_ns, stream_ids, counts, dtypes, keep=None):
         """Replays a request trace (native submission at the arrival times);
-        returns (latency ns (n,), stages ns (n, 3): queued, admitted, running)."""
+        returns (latency ns (n,), stages ns (n, 3): queued, admitted, running).
+        keep: optional sequence of n device addresses (0 = drop) where the
+        results of chosen requests are copied."""
         ta = np.ascontiguousarray(t_arrival_ns, dtype=np.uint64)
         st = np.ascontiguousarray(stream_ids, dtype=np.int32)
         ct = np.ascontiguousarray(counts, dtype=np.uint64)
@@ -469,10 +473,22 @@ class Server:
         n = int(ta.shape[0])
         lat = np.zeros(n, dtype=np.uint64)
         stg = np.zeros((n, 3), dtype=np.uint64)
+        kp = None
+        if keep is not None:
+            kp = np.ascontiguousarray([_ptr(x) for x in keep], dtype=np.uint64)
+            if kp.shape[0] != n:
+                raise ValueError("keep needs one entry per request")
         _check(lib().mtgp_server_replay(self.h, ta.ctypes.data, st.ctypes.data, ct.ctypes.data,
-                                        dt.ctypes.data, n, lat.ctypes.data, stg.ctypes.data),
+                                        dt.ctypes.data, n, lat.ctypes.data, stg.ctypes.data,
+                                        kp.ctypes.data if kp is not None else None),
                "mtgp_server_replay")
         return lat, stg
+
+    def repaired(self) -> int:
+        """Requests regenerated after a failed jump-ahead segment check."""
+        v = ctypes.c_uint64()
+        _check(lib().mtgp_server_repaired(self.h, ctypes.byref(v)), "mtgp_server_repaired")
+        return int(v.value)
 
     def poll(self, ticket: int):
         st = ctypes.c_int()
@@ -504,5 +520,6 @@ class Server:
 
     def close(self) -> None:
         if self.h:
-            _check(lib().mtgp_server_destroy(self.h), "mtgp_server_destroy")
-            self.h = None
+            h, self.h = self.h, None
+            _check(lib().mtgp_server_destroy(h), "mtgp_server_destroy")
+        self.pool = None  # the output pool's device memory goes back to torch

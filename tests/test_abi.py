@@ -134,10 +134,10 @@ def test_strerror(lib):
 
 
 def test_batch_workspace_size(lib):
-    # header + 80-byte items + one countdown word per request, 256-aligned
+    # header + one 80-byte item per request, 256-aligned
     assert mtgp.batch_workspace_bytes(0) == 256
-    assert mtgp.batch_workspace_bytes(10) == 256 + 1024 + 256
-    assert mtgp.batch_workspace_bytes(1000) == 256 + 80128 + 4096
+    assert mtgp.batch_workspace_bytes(10) == 256 + 1024
+    assert mtgp.batch_workspace_bytes(1000) == 256 + 80128
 
 
 def test_library_has_no_oracle_dependency():

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from orbit_check import annihilates
 from paper_1501_07701_amd import mtgp, workloads
 
 pytestmark = pytest.mark.gpu
@@ -166,4 +167,99 @@ def test_phase_timing_stamps(torch):
             o, _ = oracle.generate(p[k], states[k], count, False)
             assert np.array_equal(_host(outs[k]), np.asarray(o).view(np.uint32)), k
             assert np.array_equal(first[k], _host(outs[k])), k
+        g.close()
+
+
+def _foreign_states(p, n_words, rng):
+    """States a stream could be restored to: exported from the same
+    parameter sets run from other seeds, and uniformly random full states."""
+    k = p.shape[0]
+    other = np.stack([oracle.seed(1000 + i, n_words) for i in range(k)])
+    moved, other = oracle.generate_many(p, other, 5000, False)
+    rand = rng.integers(0, 2**32, (k, n_words), dtype=np.uint64).astype(np.uint32)
+    return np.where((np.arange(k) % 2 == 0)[:, None], other, rand)
+
+
+@pytest.mark.parametrize("mexp,count", [(3217, 60000), (11213, 150000)])
+def test_load_params_import_then_split(torch, mexp, count):
+    """Checkpoint-restore flow: parameters uploaded without seeds, states
+    imported from elsewhere (other seeds' streams, random full states);
+    split batches from there are exact, with no segment-check repairs (the
+    polynomials are built from the imported states)."""
+    _say("case load_params + import + split mexp=%d" % mexp)
+    N = mexp // 32 + 1
+    p = _params(mexp, 0x1A + mexp)
+    n = p.shape[0]
+    st = _foreign_states(p, N, np.random.default_rng(mexp))
+    d_params = torch.empty(n * mtgp.DEVICE_PARAM_BYTES, dtype=torch.uint8, device="cuda")
+    d_states = torch.empty(n * N, dtype=torch.int32, device="cuda")
+    mtgp.load_params(p, d_params)
+    mtgp.state_import(d_params, d_states, N, st)
+    counts = [count, count // 2 + 7, count, 3 * count // 4 + 1, 1000, count]
+    dts = [0, 1, 0, 1, 0, 1]
+    with _Tune(mexp, 256):
+        outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in counts]
+        items = [(k, dts[k], counts[k], outs[k]) for k in range(n)]
+        ws = torch.empty(mtgp.batch_workspace_query(d_params, items), dtype=torch.uint8,
+                         device="cuda")
+        states = st.copy()
+        for rep in range(2):
+            mtgp.generate_batch(d_params, d_states, N, items, ws)
+            got = [_host(o).copy() for o in outs]
+            assert mtgp.batch_errors(ws) == 0, rep
+            for k in range(n):
+                o, states[k] = oracle.generate(p[k], states[k], counts[k], bool(dts[k]))
+                assert np.array_equal(got[k], np.asarray(o).view(np.uint32)), (rep, k)
+        assert np.array_equal(mtgp.state_export(d_params, d_states, N, n, N), states)
+        # the data is really split: a minimum workspace cannot hold the plan
+        assert ws.numel() > mtgp.batch_workspace_bytes(n)
+    mtgp.release_params(d_params)
+
+
+def test_states_written_behind_the_library_are_repaired(torch):
+    """States written straight into device memory (no import) can lie
+    outside the orbit a stream's polynomial annihilates: the segment checks
+    fail, the device regenerates those requests in order, the outputs stay
+    exact, the repairs are reported, and the next call rebuilds the
+    polynomials from the current states (no repairs)."""
+    _say("case repair after states written behind the library")
+    mexp, count = 3217, 60000
+    N = mexp // 32 + 1
+    p = workloads.make_params(mexp, 16, 0x4E9A)
+    seeds = np.zeros(16, dtype=np.uint32)          # seed status 0 (paper, Sec. 5.1)
+    with _Tune(mexp, 256):
+        g = mtgp.Generators(p, seeds)
+        deg, co = mtgp.stream_polynomials(g.d_params, 16, mexp)
+        # random states whose word sequence the stream's polynomial (built
+        # from the seed-0 orbit) does not annihilate, checked with the oracle
+        rng = np.random.default_rng(7)
+        st = g.states_host()
+        low = []
+        for k in range(16):
+            if len(low) == 4 or deg[k] <= 0:
+                continue
+            for _ in range(4):
+                cand = rng.integers(0, 2**32, N, dtype=np.uint64).astype(np.uint32)
+                if not annihilates(p[k], co[k], int(deg[k]), cand):
+                    st[k] = cand
+                    low.append(k)
+                    break
+        assert len(low) >= 2, deg                  # seed-0 orbits of random sets
+        # behind the library's back: a device copy, not mtgp_state_import
+        g.d_states.copy_(torch.from_numpy(st.view(np.int32).reshape(-1)).to("cuda"))
+        outs = [torch.empty(count, dtype=torch.int32, device="cuda") for _ in low]
+        items = [(k, i & 1, count, outs[i]) for i, k in enumerate(low)]
+        ws = g.workspace(items)
+        states = st.copy()
+        repairs = []
+        for rep in range(2):
+            g.batch(items, ws)
+            got = [_host(o).copy() for o in outs]
+            repairs.append(mtgp.batch_errors(ws))
+            for i, k in enumerate(low):
+                o, states[k] = oracle.generate(p[k], states[k], count, bool(i & 1))
+                assert np.array_equal(got[i], np.asarray(o).view(np.uint32)), (rep, k)
+        assert np.array_equal(g.states_host(), states)
+        assert repairs[0] >= 1, repairs            # the checks caught the wrong orbits
+        assert repairs[1] == 0, repairs            # rebuilt from the current states
         g.close()

@@ -2,8 +2,8 @@
 
 Small cases span several steps, buffer compactions and ragged tails, for
 every supported mexp and every compiled launch tuning; the full-size
-workloads are checked on sampled streams (the oracle runs each sampled
-stream from its initial state) plus properties that hold at any size.
+workloads (128 x 2^24 through the benchmarked batch path, 4096 x 2^20,
+1024 streams of log-uniform length) are checked on every stream.
 Tolerance: none.  uint32 outputs, float32 bit patterns and final states must
 be identical.
 """
@@ -284,76 +284,117 @@ def test_autotune_keeps_results_identical(torch):
 
 # ------------------------------------------------------- full-size runs ---
 
-def test_c2_full_size_sampled(torch):
-    """128 streams x 2^24 as uint32, then as float32 from the same initial
-    states; sampled streams against the oracle, the float identity
-    bits(f + 1) == 0x3F800000 | (u >> 9) on every output."""
-    _say("case C2 full size")
+def _compare_streams(get_out, params, states0, counts, flts, chunk=16, threads=16):
+    """Every stream's outputs against the oracle, `chunk` streams at a time
+    (get_out(k) -> host uint32 array of stream k); returns the oracle's
+    final states."""
+    n = params.shape[0]
+    counts = np.broadcast_to(np.asarray(counts, dtype=np.int64), (n,))
+    flts = np.broadcast_to(np.asarray(flts, dtype=bool), (n,))
+    final = np.array(states0, dtype=np.uint32, copy=True)
+    for c0 in range(0, n, chunk):
+        ks = list(range(c0, min(n, c0 + chunk)))
+        exp, st = oracle.generate_many(params[ks], final[ks], counts[ks], flts[ks],
+                                       threads=threads)
+        final[ks] = st
+        for j, k in enumerate(ks):
+            got = get_out(k)
+            want = np.asarray(exp[j]).view(np.uint32)
+            if not np.array_equal(got, want):
+                bad = int(np.flatnonzero(got != want)[0])
+                raise AssertionError("stream %d differs first at output %d" % (k, bad))
+    return final
+
+
+def test_c2_full_size_batch_as_benched(torch):
+    """128 streams x 2^24 (mexp 11213) exactly as the benchmark runs them:
+    re-seed, uint32 pass through mtgp_generate_batch, re-seed, float32 pass,
+    three steps (graph replays).  Every output of every stream of both
+    passes and every final state against the oracle."""
+    _say("case C2 full size, batch path as benched")
     params, seeds = workloads.config_inputs("C2")
     count = workloads.CONFIGS["C2"]["count"]
+    n = params.shape[0]
+    N = mtgp.state_words(int(params[0, 0]))
     g = mtgp.Generators(params, seeds)
-    init = g.states_host()
-    u = g.generate(count, mtgp.U32)
-    end_u = g.states_host()
-    g.load_states(init)
-    f = g.generate(count, mtgp.F32)
-    assert np.array_equal(g.states_host(), end_u)
-    ident = (f + 1.0).view(torch.int32) == (torch.bitwise_right_shift(u, 9) & 0x7FFFFF | 0x3F800000)
-    assert bool(ident.all())
-    sample = [0, 37, 127]
-    exp, exp_states = _oracle_run(params[sample], seeds[sample], [count], [False])
-    for j, k in enumerate(sample):
-        assert np.array_equal(_host(u[k * count:(k + 1) * count]), exp[j][0]), k
-        assert np.array_equal(end_u[k], exp_states[j])
+    out_u = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    out_f = torch.empty(n * count, dtype=torch.float32, device="cuda")
+    list_u = [(k, mtgp.U32, count, out_u.data_ptr() + 4 * k * count) for k in range(n)]
+    list_f = [(k, mtgp.F32, count, out_f.data_ptr() + 4 * k * count) for k in range(n)]
+    ws_u, ws_f = g.workspace(list_u), g.workspace(list_f)
+    assert ws_u.numel() > mtgp.batch_workspace_bytes(n)   # jump-ahead splits the streams
+    for step in range(3):
+        for items, ws in ((list_u, ws_u), (list_f, ws_f)):
+            g.reseed()
+            g.batch(items, ws)
+    torch.cuda.synchronize()
+    assert mtgp.batch_errors(ws_u) == 0 and mtgp.batch_errors(ws_f) == 0
+    end = g.states_host()
+    init = np.stack([oracle.seed(int(s), N) for s in seeds])
+    fin_u = _compare_streams(lambda k: _host(out_u[k * count:(k + 1) * count]),
+                             params, init, count, False)
+    fin_f = _compare_streams(lambda k: _host(out_f[k * count:(k + 1) * count]),
+                             params, init, count, True)
+    assert np.array_equal(fin_u, fin_f)
+    assert np.array_equal(end, fin_f)
     g.close()
 
 
-def test_c3_full_size_sampled(torch):
-    """4096 streams x 2^20 uint32 in one persistent graph launch (16 GiB)."""
+def test_c3_full_size_every_stream(torch):
+    """4096 streams x 2^20 uint32 (mexp 23209, 16 GiB) in one persistent
+    graph launch: every stream against the oracle."""
     _say("case C3 full size")
     params, seeds = workloads.config_inputs("C3")
     count = workloads.CONFIGS["C3"]["count"]
     n = params.shape[0]
+    N = mtgp.state_words(int(params[0, 0]))
     g = mtgp.Generators(params, seeds)
     out = torch.empty(n * count, dtype=torch.int32, device="cuda")
     items = [(k, mtgp.U32, count, out.data_ptr() + 4 * k * count) for k in range(n)]
-    g.batch(items)
+    ws = g.batch(items)
     torch.cuda.synchronize()
-    W = 726 - params[:, 1].astype(np.int64)
-    sample = sorted({int(np.argmin(W)), int(np.argmax(W)), 0, 1, 2049, 4095})
-    exp, exp_states = _oracle_run(params[sample], seeds[sample], [count], [False])
+    assert mtgp.batch_errors(ws) == 0
     st = g.states_host()
-    for j, k in enumerate(sample):
-        assert np.array_equal(_host(out[k * count:(k + 1) * count]), exp[j][0]), k
-        assert np.array_equal(st[k], exp_states[j]), k
+    init = np.stack([oracle.seed(int(s), N) for s in seeds])
+    per = 256   # streams per device-to-host copy (1 GiB)
+    cache = {}
+
+    def get(k):
+        blk = k // per
+        if blk not in cache:
+            cache.clear()
+            lo, hi = blk * per * count, min(n, (blk + 1) * per) * count
+            cache[blk] = _host(out[lo:hi])
+        return cache[blk][(k - blk * per) * count:(k - blk * per + 1) * count]
+
+    fin = _compare_streams(get, params, init, count, False, chunk=64)
+    assert np.array_equal(st, fin)
     del out
     g.close()
 
 
-def test_c4_full_size_sampled(torch):
-    """1024 streams, lengths log-uniform in [2^10, 2^24], dtype 50/50, one
-    launch; sampled streams (longest, shortest, smallest W, random)."""
+def test_c4_full_size_every_stream(torch):
+    """1024 streams of mexp 44497, lengths log-uniform in [2^10, 2^24],
+    dtype 50/50, one launch: every stream against the oracle."""
     _say("case C4 full size")
     params, seeds = workloads.config_inputs("C4")
     lens, dts = workloads.uneven_batch("C4")
     n = params.shape[0]
+    N = mtgp.state_words(int(params[0, 0]))
     offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     g = mtgp.Generators(params, seeds)
     out = torch.empty(int(offs[-1]), dtype=torch.int32, device="cuda")
     base = out.data_ptr()
     items = [(k, int(dts[k]), int(lens[k]), base + 4 * int(offs[k])) for k in range(n)]
-    g.batch(items)
+    ws = g.batch(items)
     torch.cuda.synchronize()
-    W = 1391 - params[:, 1].astype(np.int64)
-    sample = sorted({int(np.argmax(lens)), int(np.argmin(lens)), int(np.argmin(W)), 5, 700})
+    assert mtgp.batch_errors(ws) == 0
     st = g.states_host()
-    N = 1391
-    for k in sample:
-        o, s_end = oracle.generate(params[k], oracle.seed(int(seeds[k]), N), int(lens[k]),
-                                   bool(dts[k]))
-        got = _host(out[int(offs[k]):int(offs[k + 1])])
-        assert np.array_equal(got, np.asarray(o).view(np.uint32)), k
-        assert np.array_equal(st[k], s_end), k
+    host = _host(out)
+    init = np.stack([oracle.seed(int(s), N) for s in seeds])
+    fin = _compare_streams(lambda k: host[int(offs[k]):int(offs[k + 1])], params, init,
+                           lens.astype(np.int64), dts.astype(bool), chunk=64)
+    assert np.array_equal(st, fin)
     del out
     g.close()
 

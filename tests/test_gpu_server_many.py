@@ -85,3 +85,94 @@ def test_replay_advances_streams_like_the_oracle(torch):
             _, states[k] = oracle.generate(p[k], states[k], tot, False)
     assert np.array_equal(g.states_host(), states)
     g.close()
+
+
+def test_c5_scale_replay_mirrored_streams(torch):
+    """Serving at the C5 shape: 16384 resident mexp-11213 streams, a 64 GB
+    output pool, requests with log-uniform lengths in [2^8, 2^24] and mixed
+    dtype arriving as a Poisson process.  64 mirrored streams (every 256th)
+    receive every fourth request; their results are kept and each one is
+    compared with the oracle, and the same requests replayed alone (a fresh
+    server from the same initial states, no other traffic) give the same
+    results.  Every touched stream's final state matches the oracle."""
+    print("case server C5 scale, mirrored streams", flush=True)
+    sys.stdout.flush()
+    cfg = workloads.CONFIGS["C5"]
+    params, seeds = workloads.config_inputs("C5")
+    n_streams, mexp = params.shape[0], cfg["mexp"]
+    N = mexp // 32 + 1
+    n_req = 3000
+    tr = workloads.request_trace(n_req, 200e3, n_streams, len_log2=cfg["len_log2"],
+                                 p_float=cfg["p_float"], master=cfg["master"])
+    st = tr["stream"].copy()
+    mirrored = np.arange(0, n_streams, 256)
+    sel = np.arange(n_req) % 4 == 0
+    st[sel] = mirrored[np.arange(int(sel.sum())) % mirrored.size]
+    L, dt = tr["length"].astype(np.uint64), tr["dtype"].astype(np.int32)
+    arr = (tr["t_arrival"] * 1e9).astype(np.uint64)
+    keep_idx = np.flatnonzero(np.isin(st, mirrored))
+    offs = np.zeros(n_req, dtype=np.int64)
+    offs[keep_idx] = np.concatenate([[0], np.cumsum(L[keep_idx].astype(np.int64))[:-1]])
+    total_kept = int(L[keep_idx].sum())
+    kept = torch.empty(total_kept, dtype=torch.int32, device="cuda")
+    kp = [0] * n_req
+    for i in keep_idx:
+        kp[int(i)] = kept.data_ptr() + 4 * int(offs[i])
+
+    g = mtgp.Generators(params, seeds)
+    srv = mtgp.Server(g, cfg["pool_bytes"], inflight=16, max_batch_items=128,
+                      batch_window_ns=50000, workspace_bytes_per_batch=128 << 20)
+    try:
+        lat, _ = srv.replay(arr, st, L, dt, keep=kp)
+        repaired = srv.repaired()
+    finally:
+        srv.close()
+    assert (lat > 0).all()
+    assert repaired == 0
+    end_states = g.states_host()
+    g.close()
+
+    # every kept result against the oracle, per stream in submission order
+    host = kept.cpu().numpy().view(np.uint32)
+    init = np.stack([oracle.seed(int(seeds[k]), N) for k in range(n_streams)])
+
+    def one_stream(k):
+        s = init[k].copy()
+        for i in np.flatnonzero(st == k):
+            o, s = oracle.generate(params[k], s, int(L[i]), bool(dt[i]))
+            got = host[int(offs[i]):int(offs[i]) + int(L[i])]
+            assert np.array_equal(got, np.asarray(o).view(np.uint32)), (k, int(i))
+        return s
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        fins = list(ex.map(one_stream, [int(k) for k in mirrored]))
+    for k, s in zip(mirrored, fins):
+        assert np.array_equal(end_states[int(k)], s), int(k)
+
+    # every other touched stream's final state
+    others = sorted(set(int(k) for k in st) - set(int(k) for k in mirrored))
+
+    def advance(k):
+        tot = int(L[st == k].sum())
+        _, s = oracle.generate(params[k], init[k], tot, False)
+        return s
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        fins = list(ex.map(advance, others))
+    for k, s in zip(others, fins):
+        assert np.array_equal(end_states[k], s), k
+
+    # the mirrored streams' requests alone, same initial states
+    g2 = mtgp.Generators(params, seeds)
+    alone = torch.empty(total_kept, dtype=torch.int32, device="cuda")
+    kp2 = [alone.data_ptr() + 4 * int(offs[i]) for i in keep_idx]
+    srv2 = mtgp.Server(g2, cfg["pool_bytes"], inflight=16, max_batch_items=128,
+                       batch_window_ns=50000, workspace_bytes_per_batch=128 << 20)
+    try:
+        srv2.replay(arr[keep_idx], st[keep_idx], L[keep_idx], dt[keep_idx], keep=kp2)
+    finally:
+        srv2.close()
+    torch.cuda.synchronize()
+    assert torch.equal(alone, kept)
+    g2.close()
