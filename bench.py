@@ -182,7 +182,7 @@ def run_c2(args):
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = min(16, len(os.sched_getaffinity(0)))
+        threads = _threads()
         log("cpu baseline: oracle on %d threads ..." % threads)
         cv, dt = cpu_baseline(params, seeds, count, threads)
         log("cpu baseline: oracle on 1 thread ...")
@@ -194,7 +194,7 @@ def run_c2(args):
                          "%.2f s wall on %d threads" % (dt, threads),
                "value_1_thread": round(cv1, 4),
                "sample_1_thread": "8 streams x 2^22 outputs, both passes, %.2f s" % dt1,
-               "cpu_model": cpu_model()}
+               "cpu_model": cpu_model(), **_host_cpus()}
 
     line = {
         "metric": "G uint32/s and % HBM write roofline",
@@ -258,7 +258,16 @@ def cpu_sample(params, seeds, counts, dtypes, threads):
 
 
 def _threads():
+    """Oracle threads: every CPU this process may run on, capped at the 16
+    host threads one GPU's share of the machine provides."""
     return min(16, len(os.sched_getaffinity(0)))
+
+
+def _host_cpus():
+    return {"host_logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "threads_note": "oracle threads = min(affinity CPUs, 16): 16 host threads "
+                            "are one GPU's share of the machine"}
 
 
 def _timed_steps(torch, step, warmup, steps):
@@ -679,12 +688,32 @@ def run_device_api(args):
                     "min_step_width": int(W.min())})
 
 
-def run_c5(args):
-    """Serving: 16384 resident mexp-11213 streams; Poisson arrivals of
-    requests with log-uniform lengths in [2^8, 2^24] and mixed dtype at
-    fractions of the saturation rate, replayed by the library's native trace
-    replay; p50/p99 latency (scheduled arrival to completion) against one
-    launch per request served FIFO on one HIP stream."""
+def _replay_stats(srv, trace_t, rate, st, L, dt, total):
+    """Replays the trace at `rate` requests/s on srv: p50/p99 latency
+    (scheduled arrival to completion) and the served output rate."""
+    import numpy as np
+    arr = (trace_t / rate * 1e9).astype(np.uint64)
+    lat, stg = srv.replay(arr, st, L, dt)
+    span = float((arr.astype(np.float64) + lat).max()) * 1e-9
+    return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e-6, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
+            "p50_ms_queued_admitted_running": [round(float(np.percentile(stg[:, c], 50)) * 1e-6,
+                                                     3) for c in range(3)],
+            "served_G_per_s": round(total / span / 1e9, 3)}
+
+
+def serve_c5(args, n_req, server_fracs, base_fracs):
+    """C5 serving measurement: 16384 resident mexp-11213 streams, a Poisson
+    trace of n_req requests (lengths log-uniform in [2^8, 2^24], mixed
+    dtype), replayed by the library's native replay on
+      - the continuous-batching server (16 launches in flight, up to 128
+        requests per launch), at fractions of its measured saturation rate;
+      - one launch per request: the same server code with one launch slot
+        and one request per launch, replayed on the same arrival clock at
+        fractions of ITS measured capacity (below and above it), and the
+        batching server at those same rates.
+    The first pass over the trace is a warm-up: it builds the jump-ahead
+    polynomials of the streams whose requests are split."""
     import numpy as np
     import torch
     from paper_1501_07701_amd import mtgp, workloads
@@ -692,7 +721,6 @@ def run_c5(args):
     cfg = workloads.CONFIGS["C5"]
     params, seeds = workloads.config_inputs("C5")
     n_streams, mexp = params.shape[0], cfg["mexp"]
-    n_req = args.requests
     g = mtgp.Generators(params, seeds)
     lo, hi = cfg["len_log2"]
     trace = workloads.request_trace(n_req, 1.0, n_streams, len_log2=(lo, hi),
@@ -700,81 +728,86 @@ def run_c5(args):
     L = trace["length"].astype(np.uint64)
     st, dt = trace["stream"], trace["dtype"]
     total = float(L.sum())
-    # server warm-up: the jump-ahead polynomial of every resident stream
-    log("warm-up: stream polynomials ...")
-    t0 = time.perf_counter()
-    mtgp.stream_polynomials(g.d_params, n_streams, mexp)
-    t_warm = time.perf_counter() - t0
+    zero = np.zeros(n_req, dtype=np.uint64)
     srv = mtgp.Server(g, cfg["pool_bytes"], inflight=args.inflight, max_batch_items=128,
                       batch_window_ns=int(args.batch_window_us * 1000),
                       workspace_bytes_per_batch=128 << 20)
+    base = None
     try:
-        # saturation: every request arrives at once (the first pass also
-        # builds the jump-ahead data of the streams the trace touches)
-        zero = np.zeros(n_req, dtype=np.uint64)
-        log("saturation pass 1 ...")
+        log("C5 warm-up pass (builds jump-ahead polynomials) ...")
+        t0 = time.perf_counter()
         srv.replay(zero, st, L, dt)
-        log("saturation pass 2 ...")
+        t_warm = time.perf_counter() - t0
+        log("C5 saturation ...")
         lat0, _ = srv.replay(zero, st, L, dt)
-        sat_outputs_s = total / (float(lat0.max()) * 1e-9)
-        lam_sat = sat_outputs_s / float(L.mean())
+        sat = total / (float(lat0.max()) * 1e-9)
+        lam_sat = sat / float(L.mean())
         rates = []
-        for f in (0.25, 0.5, 0.75, 0.9, 1.0, 1.2):
-            lam = f * lam_sat
-            log("rate %.2f x saturation (%.0f req/s) ..." % (f, lam))
-            arr = (trace["t_arrival"] / lam * 1e9).astype(np.uint64)
-            lat, stg = srv.replay(arr, st, L, dt)
-            span = float((arr.astype(np.float64) + lat).max()) * 1e-9
-            rates.append({"frac": f, "req_per_s": round(lam, 1),
-                          "p50_ms": round(float(np.percentile(lat, 50)) * 1e-6, 3),
-                          "p99_ms": round(float(np.percentile(lat, 99)) * 1e-6, 3),
-                          "p50_ms_queued_admitted_running": [
-                              round(float(np.percentile(stg[:, c], 50)) * 1e-6, 3)
-                              for c in range(3)],
-                          "served_G_per_s": round(total / span / 1e9, 3)})
+        for f in server_fracs:
+            log("C5 batching server at %.2f x its saturation ..." % f)
+            r = {"frac_of_server_saturation": f, "req_per_s": round(f * lam_sat, 1)}
+            r["server"] = _replay_stats(srv, trace["t_arrival"], f * lam_sat, st, L, dt, total)
+            rates.append(r)
+        base = mtgp.Server(g, cfg["pool_bytes"], inflight=1, max_batch_items=1,
+                           batch_window_ns=0, workspace_bytes_per_batch=128 << 20)
+        log("C5 one launch per request: capacity ...")
+        lat_b, _ = base.replay(zero, st, L, dt)
+        base_sat = total / (float(lat_b.max()) * 1e-9)
+        lam_base = base_sat / float(L.mean())
+        for f in base_fracs:
+            lam = f * lam_base
+            log("C5 both at %.2f x the one-launch capacity ..." % f)
+            r = {"frac_of_one_launch_capacity": f, "req_per_s": round(lam, 1)}
+            r["one_launch_per_request"] = _replay_stats(base, trace["t_arrival"], lam, st, L, dt,
+                                                        total)
+            r["server"] = _replay_stats(srv, trace["t_arrival"], lam, st, L, dt, total)
+            rates.append(r)
+        repaired = srv.repaired() + base.repaired()
     finally:
         srv.close()
+        if base is not None:
+            base.close()
+        g.close()
+    return {"workload": cfg["name"], "mexp": mexp, "resident_streams": n_streams,
+            "requests_per_replay": n_req, "mean_request_outputs": round(float(L.mean())),
+            "pool_bytes": cfg["pool_bytes"], "inflight_batches": args.inflight,
+            "max_batch_items": 128, "batch_window_us": args.batch_window_us,
+            "server_saturation_G_per_s": round(sat / 1e9, 3),
+            "server_saturation_req_per_s": round(lam_sat, 1),
+            "one_launch_per_request_capacity_G_per_s": round(base_sat / 1e9, 3),
+            "one_launch_per_request_capacity_req_per_s": round(lam_base, 1),
+            "warmup_pass_s": round(t_warm, 2),
+            "segment_check_repairs": repaired,
+            "rates": rates,
+            "note": "latency = completion - scheduled arrival, native trace replay; "
+                    "one launch per request = the same server with one launch slot "
+                    "and one request per launch"}
 
-    # one launch per request, FIFO on one HIP stream: each request's
-    # service time measured alone (host planning + launch + completion),
-    # then queued at the same arrival times
-    log("one launch per request ...")
-    nb = min(n_req, 1000)
-    buf = torch.empty(int(L[:nb].max()), dtype=torch.int32, device="cuda")
-    w1 = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
-    d = np.zeros(nb)
-    for i in range(nb):
-        it = [(int(st[i]), int(dt[i]), int(L[i]), buf.data_ptr())]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        mtgp.generate_batch(g.d_params, g.d_states, g.stride, it, w1)
-        torch.cuda.synchronize()
-        d[i] = time.perf_counter() - t0
-    base_outputs_s = float(L[:nb].sum()) / d.sum()
-    for r in rates:
-        arr = trace["t_arrival"][:nb] / r["req_per_s"]
-        fin_t = np.zeros(nb)
-        t = 0.0
-        for i in range(nb):
-            t = max(t, arr[i]) + d[i]
-            fin_t[i] = t
-        lat = fin_t - arr
-        r["one_launch_per_request_p50_ms"] = round(float(np.percentile(lat, 50)) * 1e3, 3)
-        r["one_launch_per_request_p99_ms"] = round(float(np.percentile(lat, 99)) * 1e3, 3)
-    line = _common(args, sat_outputs_s / 1e9, "G outputs/s", 0.0,
-                   {"workload": cfg["name"], "mexp": mexp, "resident_streams": n_streams,
-                    "requests_per_rate": n_req, "mean_request_outputs": round(float(L.mean())),
-                    "inflight_batches": args.inflight, "batch_window_us": args.batch_window_us,
-                    "max_batch_items": 128},
-                   None, None,
-                   {"saturation_req_per_s": round(lam_sat, 1),
-                    "warmup_polynomials_s": round(t_warm, 2),
-                    "one_launch_per_request_G_per_s": round(base_outputs_s / 1e9, 3),
-                    "rates": rates})
+
+def run_c5(args):
+    """Serving (C5) as its own bench line: the full rate sweep."""
+    res = serve_c5(args, args.requests, (0.25, 0.5, 0.75, 0.9, 1.0, 1.2), (0.5, 2.0))
+    line = _common(args, res["server_saturation_G_per_s"], "G outputs/s", 0.0,
+                   {k: res[k] for k in ("workload", "mexp", "resident_streams",
+                                        "requests_per_replay", "mean_request_outputs",
+                                        "inflight_batches", "batch_window_us",
+                                        "max_batch_items")},
+                   None, None, {k: v for k, v in res.items()
+                                if k not in ("workload", "mexp", "resident_streams")})
     line["metric"] = "served G outputs/s at saturation; p50/p99 latency per arrival rate"
     line["steps"] = 0
     line["warmup"] = 0
     return line
+
+
+def _compact_c3(line):
+    keys = ("value", "unit", "ms_per_step", "avg_generate_launch_ms", "roofline",
+            "phases_us_prefix_jumps_segments", "segment_phase_GBps", "store_only_fill_GBps",
+            "autotuned", "min_step_width", "config")
+    out = {k: line[k] for k in keys if k in line}
+    out["autotuned"] = {k: v for k, v in out.get("autotuned", {}).items()
+                        if k != "candidate_ms"}
+    return out
 
 
 def main():
@@ -793,6 +826,11 @@ def main():
                     help="C5: how long a ready batch waits for more requests")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload only: skip the C3 and C5 figures added "
+                         "to the line (profiling runs)")
+    ap.add_argument("--extra-requests", type=int, default=4000,
+                    help="requests per replay in the C5 figures of the default line")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a store-only fill and a copy of known size, "
                          "the references for hardware counter scaling")
@@ -809,6 +847,17 @@ def main():
     run = {"C2": run_c2, "C3": run_c3, "C4": run_c4, "C5": run_c5, "P1": run_paper,
            "P2": run_paper, "DEV": run_device_api}[args.workload]
     line = run(args)
+    if args.workload == "C2" and not args.no_extras:
+        # the scheduler and serving rows in the same run: the autotuned
+        # C3 batch (one graph launch) and a shortened C5 sweep
+        torch.cuda.empty_cache()
+        sub = argparse.Namespace(**vars(args))
+        sub.no_cpu_baseline = True
+        sub.steps, sub.warmup = min(args.steps, 10), min(args.warmup, 2)
+        log("C3 (autotuned batch) ...")
+        line["C3"] = _compact_c3(run_c3(sub))
+        torch.cuda.empty_cache()
+        line["C5"] = serve_c5(sub, args.extra_requests, (0.5, 1.0), (0.5, 2.0))
     print(json.dumps(line), flush=True)
 
 
