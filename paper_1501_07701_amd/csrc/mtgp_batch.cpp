@@ -253,10 +253,10 @@ static int ensure_jumps(const std::shared_ptr<ParamSet> &ps, const void *d_param
         a.persistent = true;
         a.num_cus = device_cus();
         a.stream = s;
+        a.win_below = (uint32_t)tun.window_below_w;
         if ((e = launch_reset((uint32_t *)d_counter.p, s)) != hipSuccess)
             return hip_fail(e, "reset kernel");
-        int rc = launch_tuned(N, tun, a);
-        if (rc) return rc;
+        if ((e = launch_prefix(N, a)) != hipSuccess) return hip_fail(e, "prefix kernel");
         if ((e = hipMemcpyAsync(raw.data(), d_raw.p, (size_t)m * R * 4, hipMemcpyDeviceToHost,
                                 s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -530,8 +530,9 @@ static int stage_acquire(Staging &st, size_t n, uint8_t **out) {
     return MTGP_OK;
 }
 
-static int stage_copy(Staging &st, size_t lo, size_t hi, char *d_base, hipStream_t s) {
+static int stage_copy(WsState &w, size_t lo, size_t hi, char *d_base, hipStream_t s) {
     if (hi <= lo) return MTGP_OK;
+    Staging &st = w.stage;
     hipError_t e = hipMemcpyAsync(d_base + lo, st.host + lo, hi - lo, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(work list)");
     e = hipEventRecord(st.done, s);
@@ -627,7 +628,8 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
         a.items = (const BatchItem *)(ws + w.off_A);
         a.n_items = w.nA;
         a.counter = hdr + 0;
-        if ((rc = launch_tuned(ps.N, t, a))) return rc;
+        a.win_below = (uint32_t)t.window_below_w;
+        if ((e = launch_prefix(ps.N, a)) != hipSuccess) return hip_fail(e, "prefix kernel");
     }
     if ((rc = stamp(1))) return rc;
     if (w.nB) {
@@ -644,7 +646,8 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
         a.items = (const BatchItem *)(ws + w.off_F);
         a.n_items = w.nF;
         a.counter = hdr + HDR_FIX_CLAIM;
-        if ((rc = launch_tuned(ps.N, t, a))) return rc;
+        a.win_below = (uint32_t)t.window_below_w;
+        if ((e = launch_check(ps.N, a)) != hipSuccess) return hip_fail(e, "check kernel");
     }
     return stamp(3);
 }
@@ -864,13 +867,13 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
     if (w.sig == sig && !dirty && w.ps.lock() == ps) {
         // same plan: the polynomials are in place; the item tables and
         // request records (device pointers, countdowns) go up every call
-        int rc = stage_copy(w.stage, HDR_BYTES, w.tables_end, ws, s);
+        int rc = stage_copy(w, HDR_BYTES, w.tables_end, ws, s);
         if (rc) return rc;
     } else {
         w.sig = 0;
         int rc = build_plan(ps, d_params, d_states, stride, reqs, ws, ws_bytes, s, t, w);
         if (rc) return rc;
-        rc = stage_copy(w.stage, HDR_BYTES, w.up_end, ws, s);
+        rc = stage_copy(w, HDR_BYTES, w.up_end, ws, s);
         if (rc) return rc;
         w.sig = sig;
     }

@@ -139,6 +139,11 @@ int variant_count(int n_words, VariantInfo *out, int max_out);
 hipError_t launch_variant(int n_words, int tps, int k, int wpb, const LaunchArgs &a,
                           bool *found);
 hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hipStream_t s);
+// Persistent launches of the prefix kernel (items may carry MODE_RAW) and
+// of the request-check kernel (MODE_FIXUP items) for state length n_words
+// (one wave per item; a.win_below applies).
+hipError_t launch_prefix(int n_words, const LaunchArgs &a);
+hipError_t launch_check(int n_words, const LaunchArgs &a);
 int variant_slots_per_cu(int n_words, int tps, int k, int wpb);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,
                        uint32_t n_streams, hipStream_t s);

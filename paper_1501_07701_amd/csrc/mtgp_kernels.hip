@@ -423,8 +423,9 @@ struct Core {
     }
 
     // Advance one stream by item.count outputs.  A MODE_VERIFY item that
-    // ends in a state other than item.verify sets *fail.
-    template <bool F32>
+    // ends in a state other than item.verify sets *fail.  RAW: the
+    // MODE_RAW word dump is compiled in (prefix kernels only).
+    template <bool F32, bool RAW>
     static __device__ __forceinline__ void run(const uint32_t *__restrict__ prm,
                                                const BatchItem &item,
                                                uint32_t *__restrict__ buf, uint32_t lane,
@@ -448,7 +449,7 @@ struct Core {
         uint32_t *st_out = reinterpret_cast<uint32_t *>(item.state_out);
         gptr<uint32_t> raw = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.raw));
         gptr<uint32_t> gout = (gptr<uint32_t>)(reinterpret_cast<uint32_t *>(item.out));
-        const bool want_raw = (item.mode & MODE_RAW) != 0;
+        const bool want_raw = RAW && (item.mode & MODE_RAW) != 0;
 
         group_sync<TPS>();  // previous user of this buffer is done with it
         for (uint32_t i = lane; i < N; i += TPS) {
@@ -516,11 +517,14 @@ __device__ __forceinline__ uint32_t group_first(uint32_t v, uint32_t *slot) {
     }
 }
 
-template <int N, int TPS, int K, int WPB>
-__global__ void __launch_bounds__(TPS == 64 ? 64 * WPB : TPS)
-gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
-           uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
-           uint32_t persistent, uint32_t win_below, PlainArgs plain) {
+// The work loop shared by the generation kernels: claim an item (or take
+// stream `it` in plain mode), run it, raise its completion flag.
+template <int N, int TPS, int K, int WPB, bool RAW>
+__device__ __forceinline__ void gen_body(const uint32_t *__restrict__ params,
+                                         const BatchItem *__restrict__ items, uint32_t n_items,
+                                         uint32_t *__restrict__ counter,
+                                         uint32_t *__restrict__ err, uint32_t persistent,
+                                         uint32_t win_below, PlainArgs plain) {
     using C = Core<N, TPS, K>;
     extern __shared__ uint32_t lds[];
     __shared__ uint32_t s_claim;
@@ -582,9 +586,9 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
                                  ? &reinterpret_cast<ReqRec *>(item.rec)->failed
                                  : nullptr;
             if (item.mode & MODE_F32)
-                C::template run<true>(prm, item, buf, lane, fail, win_below);
+                C::template run<true, RAW>(prm, item, buf, lane, fail, win_below);
             else
-                C::template run<false>(prm, item, buf, lane, fail, win_below);
+                C::template run<false, RAW>(prm, item, buf, lane, fail, win_below);
         }
         if (item.flag != 0) {
             // Publish completion of the request to the host: every lane's
@@ -597,6 +601,42 @@ gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ it
         }
         if (!persistent) it += n_groups;
     }
+}
+
+// Segments of a batch, whole unsplit requests and plain calls.
+template <int N, int TPS, int K, int WPB>
+__global__ void __launch_bounds__(TPS == 64 ? 64 * WPB : TPS)
+gen_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
+           uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
+           uint32_t persistent, uint32_t win_below, PlainArgs plain) {
+    gen_body<N, TPS, K, WPB, false>(params, items, n_items, counter, err, persistent, win_below,
+                                    plain);
+}
+
+// Outputs per lane and step of the prefix kernel (the default tuning's).
+__host__ __device__ constexpr int prefix_k(int N) { return N <= 400 ? 4 : 8; }
+
+// Prefix items of split requests (the first D+1 outputs, dumping the raw
+// words the jump evaluation reads), and the word runs jump-ahead planning
+// takes its polynomials from: one wave per item, four waves per workgroup.
+template <int N>
+__global__ void __launch_bounds__(256)
+prefix_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
+              uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
+              uint32_t persistent, uint32_t win_below, PlainArgs plain) {
+    gen_body<N, 64, prefix_k(N), 4, true>(params, items, n_items, counter, err, persistent,
+                                          win_below, plain);
+}
+
+// Request checks of split requests (MODE_FIXUP items), after the segments:
+// usually no generation at all; a failed request is regenerated here.
+template <int N>
+__global__ void __launch_bounds__(256)
+check_kernel(const uint32_t *__restrict__ params, const BatchItem *__restrict__ items,
+             uint32_t n_items, uint32_t *__restrict__ counter, uint32_t *__restrict__ err,
+             uint32_t persistent, uint32_t win_below, PlainArgs plain) {
+    gen_body<N, 64, 1, 4, false>(params, items, n_items, counter, err, persistent, win_below,
+                                 plain);
 }
 
 // Jump evaluation: out[m] = XOR over the set bits i < D of g of r[i+m] with
@@ -779,24 +819,28 @@ fill_kernel(u32x4 *__restrict__ out, uint64_t n_vec, uint32_t *__restrict__ tail
 
 // ------------------------------------------------------------- dispatch --
 
+typedef void (*GenFn)(const uint32_t *, const BatchItem *, uint32_t, uint32_t *, uint32_t *,
+                      uint32_t, uint32_t, PlainArgs);
+
+// Launches one of the generation kernels with the LDS of Core<N, TPS, K>
+// times the groups per workgroup; persistent launches fill every CU to its
+// occupancy with no more groups than items.
 template <int N, int TPS, int K, int WPB>
-static hipError_t launch_gen(const LaunchArgs &a) {
+static hipError_t launch_with(GenFn fn, bool *attr_set, const LaunchArgs &a) {
     using C = Core<N, TPS, K>;
-    auto fn = gen_kernel<N, TPS, K, WPB>;
     const int threads = TPS == 64 ? 64 * WPB : TPS;
     const size_t lds = (size_t)C::LDS_WORDS * 4 * (TPS == 64 ? WPB : 1);
-    static bool attr_set = false;  // benign race: idempotent attribute
-    if (!attr_set) {
+    if (!*attr_set) {  // benign race: idempotent attribute
         hipError_t e = hipFuncSetAttribute((const void *)fn,
                                            hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        *attr_set = true;
     }
     const int per_block = TPS == 64 ? WPB : 1;
     const int need = (int)((a.n_items + per_block - 1) / per_block);
     int grid = need > 0 ? need : 1;
-    if (a.persistent) {  // fill every CU to its occupancy, no more groups than items
+    if (a.persistent) {
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
         if (e != hipSuccess) return e;
@@ -809,6 +853,44 @@ static hipError_t launch_gen(const LaunchArgs &a) {
                        a.items, a.n_items, a.counter, a.err, a.persistent ? 1u : 0u,
                        a.win_below, plain);
     return hipGetLastError();
+}
+
+template <int N, int TPS, int K, int WPB>
+static hipError_t launch_gen(const LaunchArgs &a) {
+    static bool attr_set = false;
+    return launch_with<N, TPS, K, WPB>(gen_kernel<N, TPS, K, WPB>, &attr_set, a);
+}
+
+template <int N>
+static hipError_t launch_prefix_n(const LaunchArgs &a) {
+    static bool attr_set = false;
+    return launch_with<N, 64, prefix_k(N), 4>(prefix_kernel<N>, &attr_set, a);
+}
+
+template <int N>
+static hipError_t launch_check_n(const LaunchArgs &a) {
+    static bool attr_set = false;
+    return launch_with<N, 64, 1, 4>(check_kernel<N>, &attr_set, a);
+}
+
+hipError_t launch_prefix(int n_words, const LaunchArgs &a) {
+    switch (n_words) {
+        case 101: return launch_prefix_n<101>(a);
+        case 351: return launch_prefix_n<351>(a);
+        case 726: return launch_prefix_n<726>(a);
+        case 1391: return launch_prefix_n<1391>(a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_check(int n_words, const LaunchArgs &a) {
+    switch (n_words) {
+        case 101: return launch_check_n<101>(a);
+        case 351: return launch_check_n<351>(a);
+        case 726: return launch_check_n<726>(a);
+        case 1391: return launch_check_n<1391>(a);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int N, int TPS, int K, int WPB>
