@@ -198,6 +198,31 @@ int mtgp_generate_batch(const void *d_params, uint32_t *d_states,
                         int n_items, void *d_workspace, size_t workspace_bytes,
                         void *stream);
 
+/* Bytes of the static device scratch that mtgp_generate_batch_noalloc uses
+ * as its batch workspace (64 MiB, one per GPU, held until the process
+ * ends). */
+#define MTGP_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* mtgp_generate_batch for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same generation, results and state advance, with the
+ * batch workspace in a static device array of MTGP_NOALLOC_SCRATCH_BYTES
+ * per GPU instead of a caller buffer.  It calls no hipMalloc, hipFree,
+ * pinned-host or other device-allocating routine (its plan is staged in
+ * ordinary host memory and copied with hipMemcpyAsync, kernels are
+ * launched directly): streams are split by jump-ahead only where their
+ * polynomial already exists (built by an earlier mtgp_generate_batch or
+ * mtgp_batch_workspace_query on the same parameter set) and only as far as
+ * the scratch holds the plan.  MTGP_ETOOBIG if even the unsplit plan of
+ * n_items requests exceeds the scratch (more than about 838,000 items).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's contents: calls that overlap on one GPU race (issue them on one
+ * stream, or synchronise between them).  Repairs after a failed segment
+ * check keep results exact but are not reported by this entry point. */
+int mtgp_generate_batch_noalloc(const void *d_params, uint32_t *d_states,
+                                int state_stride, const mtgp_work *h_items,
+                                int n_items, void *stream);
+
 /* Phase timing, for measurement.  While enabled (process-wide; default
  * off), every mtgp_generate_batch call writes four device wall-clock
  * timestamps into its workspace header: at its start, after the prefix

@@ -532,6 +532,11 @@ static int stage_acquire(Staging &st, size_t n, uint8_t **out) {
 
 static int stage_copy(WsState &w, size_t lo, size_t hi, char *d_base, hipStream_t s) {
     if (hi <= lo) return MTGP_OK;
+    if (w.no_alloc) {
+        hipError_t e = hipMemcpyAsync(d_base + lo, w.image.data() + lo, hi - lo,
+                                      hipMemcpyHostToDevice, s);
+        return e == hipSuccess ? MTGP_OK : hip_fail(e, "hipMemcpyAsync(work list)");
+    }
     Staging &st = w.stage;
     hipError_t e = hipMemcpyAsync(d_base + lo, st.host + lo, hi - lo, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(work list)");
@@ -666,17 +671,20 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         segs[i].req = (int)i;
         if (wants_split(*ps, reqs[i], T, t)) want.push_back(reqs[i].stream);
     }
-    if (!want.empty()) {
+    if (!want.empty() && !w.no_alloc) {
         int rc = ensure_jumps(ps, d_params, d_states, stride, want, t, s);
         if (rc) return rc;
     }
     // snapshot of the streams' jump data (an entry may be replaced by a
-    // rebuild meanwhile; the snapshot keeps this plan's alive)
+    // rebuild meanwhile; the snapshot keeps this plan's alive); without
+    // building, a stream due for a rebuild is not split
     std::vector<std::shared_ptr<StreamJump>> sjs(reqs.size());
     {
         std::lock_guard<std::mutex> lk(ps->jump_mu);
-        if (ps->jumps.size() == (size_t)ps->n)
-            for (size_t i = 0; i < reqs.size(); ++i) sjs[i] = ps->jumps[reqs[i].stream];
+        if (ps->jumps.size() == (size_t)ps->n && ps->dirty.size() == (size_t)ps->n)
+            for (size_t i = 0; i < reqs.size(); ++i)
+                if (!(w.no_alloc && ps->dirty[(size_t)reqs[i].stream]))
+                    sjs[i] = ps->jumps[reqs[i].stream];
     }
     // plan, doubling the target until the workspace fits
     Layout L;
@@ -709,7 +717,12 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
     // polynomials (every byte that is read is written; the alignment gaps
     // between tables are never read).  The header is never uploaded.
     uint8_t *img = nullptr;
-    if (int rc = stage_acquire(w.stage, L.up_end, &img)) return rc;
+    if (w.no_alloc) {
+        w.image.resize(L.up_end);
+        img = w.image.data();
+    } else if (int rc = stage_acquire(w.stage, L.up_end, &img)) {
+        return rc;
+    }
     auto at = [&](size_t off) { return img + off; };
     std::vector<std::pair<uint64_t, BatchItem>> A, C;
     std::vector<JumpItem> B;
@@ -1059,6 +1072,46 @@ int mtgp_generate_batch(const void *d_params, uint32_t *d_states, int state_stri
                         size_t workspace_bytes, void *stream) {
     return batch_common(d_params, d_states, state_stride, h_items, n_items, d_workspace,
                         workspace_bytes, (hipStream_t)stream, nullptr, true, nullptr);
+}
+
+int mtgp_generate_batch_noalloc(const void *d_params, uint32_t *d_states, int state_stride,
+                                const mtgp_work *h_items, int n_items, void *stream) {
+    if (n_items < 0) return fail(MTGP_EINVAL, "n_items=%d", n_items);
+    const size_t need = batch_min_ws_bytes(n_items);
+    if (need > (size_t)MTGP_NOALLOC_SCRATCH_BYTES)
+        return fail(MTGP_ETOOBIG,
+                    "a batch of %d items needs %zu bytes of workspace; the static scratch "
+                    "holds %u",
+                    n_items, need, (unsigned)MTGP_NOALLOC_SCRATCH_BYTES);
+    auto ps = lookup_params(d_params, 0);
+    if (!ps) return MTGP_EINVAL;
+    if (!d_states || state_stride < ps->N)
+        return fail(MTGP_EINVAL, "state_stride %d < N=%d or NULL states", state_stride,
+                    ps->N);
+    int rc = validate_requests(*ps, h_items, n_items);
+    if (rc) return rc;
+    void *scr = nullptr;
+    hipError_t e = scratch_address(&scr);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    // one plan state per GPU's scratch
+    static std::mutex mu;
+    static std::map<int, std::unique_ptr<WsState>> states;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    WsState *w;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto &slot = states[dev];
+        if (!slot) {
+            slot = std::make_unique<WsState>();
+            slot->no_alloc = true;
+        }
+        w = slot.get();
+    }
+    std::lock_guard<std::mutex> lk(w->mu);
+    return run_batch(ps, d_params, d_states, state_stride, to_requests(h_items, n_items), scr,
+                     (size_t)MTGP_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream,
+                     tuning_for(ps->N), false, *w, false);
 }
 
 int mtgp_set_phase_timing(int enable) {

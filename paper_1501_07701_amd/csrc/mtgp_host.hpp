@@ -64,6 +64,11 @@ struct WsState {
     size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, tables_end = 0, up_end = 0;
     std::weak_ptr<ParamSet> ps;         // parameter set of the last plan
     std::vector<int32_t> split_streams;  // streams the last plan split
+    // no_alloc: the plan is staged in `image` (ordinary host memory, which
+    // hipMemcpyAsync has finished reading when it returns) instead of
+    // pinned memory, and no jump-ahead data is built
+    bool no_alloc = false;
+    std::vector<uint8_t> image;
 };
 
 int fail(int code, const char *fmt, ...);

@@ -156,6 +156,9 @@ hipError_t launch_clear(uint32_t *p, uint32_t n, hipStream_t s);
 // (then also the timestamps), and writes the tag.
 hipError_t launch_header(uint32_t *hdr, uint64_t tag, bool clear_errors, hipStream_t s);
 hipError_t launch_stamp(uint64_t *dst, hipStream_t s);
+// Device address of the current GPU's static scratch array (looked up once
+// per device).
+hipError_t scratch_address(void **out);
 hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t stride,
                             uint32_t n_streams, uint64_t count, uint32_t *out, uint32_t f32,
                             uint32_t threads, uint32_t n_words, hipStream_t s);

@@ -28,10 +28,38 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
+#include "mtgp.h"
 #include "mtgp_device.h"
 #include "mtgp_internal.hpp"
 
 namespace mtgp {
+
+// Batch workspace of mtgp_generate_batch_noalloc: one per GPU, held until
+// the process ends.  Host code never passes this name to a kernel (it is a
+// host-side stand-in there); it uses the device address that
+// scratch_address() looked up on that device.
+static __device__ __align__(256) uint8_t scratch[MTGP_NOALLOC_SCRATCH_BYTES];
+
+hipError_t scratch_address(void **out) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;  // per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(dev);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));  // with `dev` current
+        if (e != hipSuccess) return e;
+        it = addr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 // Pointer into global memory (address space 1), so stores are emitted as
 // global_store rather than flat_store.

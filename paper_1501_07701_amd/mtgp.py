@@ -22,6 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MTGP_LIBRARY") or os.path.join(_HERE, "_build", "libmtgp.so")
 PARAM_WORDS = 53
 DEVICE_PARAM_BYTES = 4096
+NOALLOC_SCRATCH_BYTES = 64 << 20
 U32, F32 = 0, 1
 PENDING, DONE, FAILED = 0, 1, 2
 
@@ -81,6 +82,8 @@ _SIGS = {
     "mtgp_generate_batch": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int, _VP,
                              ctypes.c_size_t, _VP], ctypes.c_int),
     "mtgp_batch_errors": ([_VP, _VP, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "mtgp_generate_batch_noalloc": ([_VP, _VP, ctypes.c_int, ctypes.POINTER(Work), ctypes.c_int,
+                                     _VP], ctypes.c_int),
     "mtgp_get_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
     "mtgp_set_tuning": ([ctypes.c_uint32, ctypes.POINTER(Tuning)], ctypes.c_int),
     "mtgp_tuning_candidates": ([ctypes.c_uint32, ctypes.POINTER(Tuning), ctypes.c_int],
@@ -253,6 +256,15 @@ def generate_batch(d_params, d_states, stride: int, items, d_workspace, stream=N
     _check(lib().mtgp_generate_batch(_ptr(d_params), _ptr(d_states), stride, arr, n,
                                      _ptr(d_workspace), wsb, _stream(stream)),
            "mtgp_generate_batch")
+
+
+def generate_batch_noalloc(d_params, d_states, stride: int, items, stream=None) -> None:
+    """mtgp_generate_batch with the library's static device scratch as the
+    workspace (no allocation)."""
+    arr, n = items if isinstance(items, tuple) else make_work(items)
+    _check(lib().mtgp_generate_batch_noalloc(_ptr(d_params), _ptr(d_states), stride, arr, n,
+                                             _stream(stream)),
+           "mtgp_generate_batch_noalloc")
 
 
 def batch_errors(d_workspace, stream=None) -> int:
