@@ -127,7 +127,7 @@ def run_c2(args):
         mtgp.generate_batch(g.d_params, g.d_states, g.stride, items, ws)
         phases[name] = [round(x, 1) for x in mtgp.batch_phase_times(ws)]
     mtgp.set_phase_timing(False)
-    seg_us = float(np.mean([phases["u32"][2], phases["f32"][2]]))
+    seg_us = float(np.mean([phases["u32"][1], phases["f32"][1]]))
     log("timing %d step(s) ..." % args.steps)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -223,8 +223,8 @@ def run_c2(args):
         "store_only_fill_GBps": round(fill_gbps, 1),
         "unsplit_critical_path_steps": crit_steps,
         "min_step_width": int(W.min()),
-        "phases_us": {"prefix_jumps_segments_u32": phases["u32"],
-                      "prefix_jumps_segments_f32": phases["f32"],
+        "phases_us": {"prefixjumps_segments_checks_u32": phases["u32"],
+                      "prefixjumps_segments_checks_f32": phases["f32"],
                       "note": "one untimed call per pass with stamp kernels between phases"},
         "segment_phase_GBps": round(n * count * 4 / (seg_us * 1e-6) / 1e9, 1),
         "jump_ahead": {"target_steps": tun.jump_target_steps,
@@ -296,8 +296,8 @@ def _phases(g, mtgp, arr, ws, out_bytes):
         us = [round(x, 1) for x in mtgp.batch_phase_times(ws)]
     finally:
         mtgp.set_phase_timing(False)
-    return {"phases_us_prefix_jumps_segments": us,
-            "segment_phase_GBps": round(out_bytes / (us[2] * 1e-6) / 1e9, 1) if us[2] else None}
+    return {"phases_us_prefixjumps_segments_checks": us,
+            "segment_phase_GBps": round(out_bytes / (us[1] * 1e-6) / 1e9, 1) if us[1] else None}
 
 
 def _pair(torch, stream):
@@ -802,7 +802,7 @@ def run_c5(args):
 
 def _compact_c3(line):
     keys = ("value", "unit", "ms_per_step", "avg_generate_launch_ms", "roofline",
-            "phases_us_prefix_jumps_segments", "segment_phase_GBps", "store_only_fill_GBps",
+            "phases_us_prefixjumps_segments_checks", "segment_phase_GBps", "store_only_fill_GBps",
             "autotuned", "min_step_width", "config")
     out = {k: line[k] for k in keys if k in line}
     out["autotuned"] = {k: v for k, v in out.get("autotuned", {}).items()

@@ -225,24 +225,19 @@ int mtgp_generate_batch_noalloc(const void *d_params, uint32_t *d_states,
 
 /* Phase timing, for measurement.  While enabled (process-wide; default
  * off), every mtgp_generate_batch call writes four device wall-clock
- * timestamps into its workspace header: at its start, after the prefix
- * items, after the jump-ahead evaluation and at its end.  Each costs a
+ * timestamps into its workspace header: at its start, after the launch
+ * that runs the prefix items and the jump-ahead evaluation, after the
+ * segments and at its end (after the request checks).  Each costs a
  * one-thread kernel launch between the phases, so leave it off for timed
  * runs.  Always MTGP_OK. */
 int mtgp_set_phase_timing(int enable);
 
-/* Synchronises `stream` and returns in h_us[0..2] the prefix, jump and
- * segment phase durations in microseconds of the last batch call on
- * d_workspace that ran with phase timing enabled.  MTGP_EINVAL if the
- * workspace holds no timestamps. */
+/* Synchronises `stream` and returns in h_us[0..2] the durations in
+ * microseconds of the prefix-and-jump launch, the segment launch and the
+ * request checks of the last batch call on d_workspace that ran with phase
+ * timing enabled.  MTGP_EINVAL if the workspace holds no timestamps. */
 int mtgp_batch_phase_times(void *d_workspace, void *stream, double *h_us);
 
-/* Synchronises `stream`, returns in *n the number of requests that batches
- * on this workspace regenerated after a failed jump-ahead segment check
- * since the count was last read (zero when the library first saw the
- * workspace), and resets it.  A nonzero count also marks the repaired
- * streams (up to eight logged by the device, else every stream the last
- * plan split) for a polynomial rebuild from their current states. */
 int mtgp_batch_errors(void *d_workspace, void *stream, uint32_t *n);
 
 /* Launch tuning for one mexp: threads per stream (64 = one wave per stream,

@@ -399,7 +399,8 @@ struct Seg {
 };
 
 struct Layout {
-    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, off_rec = 0, off_poly = 0, up_end = 0;
+    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, off_rec = 0, off_jdep = 0, off_pflag = 0;
+    size_t off_poly = 0, up_end = 0;
     size_t off_raw = 0, off_js = 0, total = 0;
 };
 
@@ -494,7 +495,9 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs) {
     L.off_C = L.off_B + al256(nB * sizeof(JumpItem));
     L.off_F = L.off_C + al256(nC * sizeof(BatchItem));
     L.off_rec = L.off_F + al256(nA * sizeof(BatchItem));
-    L.off_poly = L.off_rec + al256(nA * sizeof(ReqRec));
+    L.off_jdep = L.off_rec + al256(nA * sizeof(ReqRec));
+    L.off_pflag = L.off_jdep + al256(nB / JUMP_BLOCK * 4);
+    L.off_poly = L.off_pflag + al256(nA * 4);
     L.up_end = L.off_poly + al256(poly_words * 4);
     L.off_raw = L.up_end;
     L.off_js = L.off_raw + al256(raw_words * 4);
@@ -608,7 +611,7 @@ static uint64_t header_tag(const void *d_ws) {
 }
 
 // Launches the phases of the workspace's planned batch on `s`: header,
-// prefix items, jump evaluation, segments, request checks.
+// prefix items and jump evaluation (one launch), segments, request checks.
 static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, const WsState &w,
                          const mtgp_tuning &t, hipStream_t s, bool stamps, bool clear_errors) {
     uint32_t *hdr = (uint32_t *)ws;
@@ -629,24 +632,21 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
     a.persistent = true;
     a.num_cus = device_cus();
     a.stream = s;
-    if (w.nA) {
-        a.items = (const BatchItem *)(ws + w.off_A);
-        a.n_items = w.nA;
-        a.counter = hdr + 0;
-        a.win_below = (uint32_t)t.window_below_w;
-        if ((e = launch_prefix(ps.N, a)) != hipSuccess) return hip_fail(e, "prefix kernel");
+    if (w.nA || w.nB) {  // prefix items and jump blocks, one launch
+        if ((e = launch_prefix_jumps(ps.N, (const BatchItem *)(ws + w.off_A), w.nA,
+                                     (const JumpItem *)(ws + w.off_B), w.nB,
+                                     (const uint32_t *)(ws + w.off_jdep),
+                                     (uint32_t *)(ws + w.off_pflag), (const uint32_t *)d_params,
+                                     hdr, (uint32_t)t.window_below_w, device_cus(), s)) !=
+            hipSuccess)
+            return hip_fail(e, "prefix and jump kernel");
     }
     if ((rc = stamp(1))) return rc;
-    if (w.nB) {
-        if ((e = launch_jump((const JumpItem *)(ws + w.off_B), w.nB, device_cus(), s)) !=
-            hipSuccess)
-            return hip_fail(e, "jump kernel");
-    }
-    if ((rc = stamp(2))) return rc;
     a.items = (const BatchItem *)(ws + w.off_C);
     a.n_items = w.nC;
     a.counter = hdr + 1;
     if ((rc = launch_tuned(ps.N, t, a))) return rc;
+    if ((rc = stamp(2))) return rc;
     if (w.nF) {  // request checks of the split requests
         a.items = (const BatchItem *)(ws + w.off_F);
         a.n_items = w.nF;
@@ -724,8 +724,9 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         return rc;
     }
     auto at = [&](size_t off) { return img + off; };
-    std::vector<std::pair<uint64_t, BatchItem>> A, C;
-    std::vector<JumpItem> B;
+    std::vector<std::pair<uint64_t, BatchItem>> C;
+    std::vector<std::tuple<uint64_t, BatchItem, size_t>> A;  // steps, item, split index
+    std::vector<std::vector<JumpItem>> Bs;                   // per split request, padded
     std::vector<BatchItem> F;
     std::vector<int32_t> split_streams;
     size_t raw_off = L.off_raw, js_off = L.off_js, poly_off = L.off_poly;
@@ -780,10 +781,12 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         a.state_in = (uint64_t)(uintptr_t)row;
         a.state_out = (uint64_t)(uintptr_t)js;
         a.raw = (uint64_t)(uintptr_t)raw;
-        A.emplace_back((P + so - 1) / so, a);
+        A.emplace_back((P + so - 1) / so, a, ri);
         // B: jumps, segment k >= 1 starts at output (c0+k-1)*lseg and
         // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words
         const size_t pw = ((size_t)D + 31) / 32;
+        Bs.emplace_back();
+        std::vector<JumpItem> &B = Bs.back();
         for (int k = 1; k < g.C; ++k) {
             const uint64_t c = g.c0 + (uint64_t)k - 1;
             JumpItem j;
@@ -821,22 +824,37 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         }
     }
     auto lpt = [](const auto &x, const auto &y) { return x.first > y.first; };
-    std::stable_sort(A.begin(), A.end(), lpt);
+    std::stable_sort(A.begin(), A.end(),
+                     [](const auto &x, const auto &y) { return std::get<0>(x) > std::get<0>(y); });
     std::stable_sort(C.begin(), C.end(), lpt);
+    // prefixes longest first; jump blocks of the streams with the shortest
+    // prefixes first (their words are ready soonest), each block naming its
+    // stream's prefix item
     for (size_t i = 0; i < A.size(); ++i)
-        std::memcpy(at(L.off_A) + i * sizeof(BatchItem), &A[i].second, sizeof(BatchItem));
-    if (!B.empty()) std::memcpy(at(L.off_B), B.data(), B.size() * sizeof(JumpItem));
+        std::memcpy(at(L.off_A) + i * sizeof(BatchItem), &std::get<1>(A[i]), sizeof(BatchItem));
+    std::memset(at(L.off_pflag), 0, A.size() * 4);
+    size_t nb = 0;
+    for (size_t i = A.size(); i-- > 0;) {
+        const std::vector<JumpItem> &B = Bs[std::get<2>(A[i])];
+        for (size_t j = 0; j < B.size(); j += JUMP_BLOCK, ++nb) {
+            std::memcpy(at(L.off_B) + nb * JUMP_BLOCK * sizeof(JumpItem), &B[j],
+                        JUMP_BLOCK * sizeof(JumpItem));
+            ((uint32_t *)at(L.off_jdep))[nb] = (uint32_t)i;
+        }
+    }
     for (size_t i = 0; i < C.size(); ++i)
         std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].second, sizeof(BatchItem));
     if (!F.empty()) std::memcpy(at(L.off_F), F.data(), F.size() * sizeof(BatchItem));
     w.nA = (uint32_t)A.size();
-    w.nB = (uint32_t)B.size();
+    w.nB = (uint32_t)(nb * JUMP_BLOCK);
     w.nC = (uint32_t)C.size();
     w.nF = (uint32_t)F.size();
     w.off_A = L.off_A;
     w.off_B = L.off_B;
     w.off_C = L.off_C;
     w.off_F = L.off_F;
+    w.off_jdep = L.off_jdep;
+    w.off_pflag = L.off_pflag;
     w.tables_end = L.off_poly;
     w.up_end = L.up_end;
     w.ps = ps;

@@ -61,7 +61,8 @@ struct WsState {
     Staging stage;
     uint64_t sig = 0;          // plan signature, 0 = no plan
     uint32_t nA = 0, nB = 0, nC = 0, nF = 0;  // prefix, jump, segment, check items
-    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, tables_end = 0, up_end = 0;
+    size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, off_jdep = 0, off_pflag = 0;
+    size_t tables_end = 0, up_end = 0;
     std::weak_ptr<ParamSet> ps;         // parameter set of the last plan
     std::vector<int32_t> split_streams;  // streams the last plan split
     // no_alloc: the plan is staged in `image` (ordinary host memory, which

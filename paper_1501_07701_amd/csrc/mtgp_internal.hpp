@@ -88,13 +88,15 @@ static_assert(sizeof(BatchItem) == 80, "BatchItem layout");
 //   word 13, 14 tag: a 64-bit value derived from the workspace address; a
 //               header without it (fresh or reused memory) is cleared by
 //               the first launch of the next call
-//   byte 64..95 phase timestamps (64-bit: start, after the prefix items,
-//               after the jump-ahead evaluation, end)
+//   word 15     claim counter of the jump blocks
+//   byte 64..95 phase timestamps (64-bit: start, after the prefix and
+//               jump launch, after the segments, end)
 constexpr int HDR_ERR = 2;
 constexpr int HDR_LOG_MAX = 8;
 constexpr int HDR_ERR_WORDS = 2 + HDR_LOG_MAX;  // words HDR_ERR .. HDR_ERR + 9
 constexpr int HDR_FIX_CLAIM = 12;
 constexpr int HDR_TAG = 13;
+constexpr int HDR_J_CLAIM = 15;
 constexpr size_t HDR_STAMP_BYTE = 64;
 constexpr size_t HDR_BYTES = 256;
 
@@ -143,6 +145,12 @@ hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hip
 // of the request-check kernel (MODE_FIXUP items) for state length n_words
 // (one wave per item; a.win_below applies).
 hipError_t launch_prefix(int n_words, const LaunchArgs &a);
+// Prefix items (nP, one wave each) and jump blocks (nJ items in blocks of
+// JUMP_BLOCK; block b waits for pflag[jdep[b]]) in one persistent launch.
+hipError_t launch_prefix_jumps(int n_words, const BatchItem *prefix, uint32_t nP,
+                               const JumpItem *jumps, uint32_t nJ, const uint32_t *jdep,
+                               uint32_t *pflag, const uint32_t *params, uint32_t *hdr,
+                               uint32_t win_below, int num_cus, hipStream_t s);
 hipError_t launch_check(int n_words, const LaunchArgs &a);
 int variant_slots_per_cu(int n_words, int tps, int k, int wpb);
 hipError_t launch_seed(const uint32_t *params, uint32_t *states, uint32_t stride,

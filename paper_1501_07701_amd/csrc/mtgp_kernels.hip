@@ -756,6 +756,33 @@ __device__ __forceinline__ void jump_pass(gptr<const uint32_t> r, gptr<const uin
     }
 }
 
+// One block of JUMP_WAVES jump items (one wave each), planes in LDS.
+__device__ __forceinline__ void jump_block(const JumpItem *__restrict__ items, uint32_t n_items,
+                                           uint32_t blk, uint32_t *__restrict__ planes,
+                                           uint32_t wave, uint32_t lane) {
+    const JumpItem lead = items[blk * JUMP_WAVES];
+    const uint32_t mine = blk * JUMP_WAVES + wave;
+    JumpItem jit = lead;
+    jit.out = 0;
+    if (mine < n_items) jit = items[mine];
+    const bool active = jit.out != 0;
+    gptr<const uint32_t> r = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(lead.raw)) + 1;
+    gptr<const uint32_t> g = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(jit.poly));
+    uint32_t *out = reinterpret_cast<uint32_t *>(jit.out);
+    const uint32_t D = lead.nbits, M = lead.m, rlen = lead.nbits + lead.m;
+    for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
+        const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
+        switch ((mt + 255) / 256) {
+#define MTGP_JP(JA) \
+    case JA: jump_pass<JA>(r, g, out, active, D, rlen, m0, mt, planes, lane); break;
+            MTGP_JP(1) MTGP_JP(2)
+#undef MTGP_JP
+            default: break;
+        }
+    }
+}
+
+// Jump evaluation alone (the planning checks of jump-ahead polynomials).
 __global__ void __launch_bounds__(64 * JUMP_WAVES)
 jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
     extern __shared__ uint32_t planes[];
@@ -763,27 +790,123 @@ jump_kernel(const JumpItem *__restrict__ items, uint32_t n_items) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t n_blocks = (n_items + JUMP_WAVES - 1) / JUMP_WAVES;
     for (uint32_t t = threadIdx.x; t < (uint32_t)JUMP_PL; t += 64 * JUMP_WAVES) planes[t] = 0u;
-    for (uint32_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x) {
-        const JumpItem lead = items[blk * JUMP_WAVES];
-        const uint32_t mine = blk * JUMP_WAVES + wave;
-        JumpItem jit = lead;
-        jit.out = 0;
-        if (mine < n_items) jit = items[mine];
-        const bool active = jit.out != 0;
-        gptr<const uint32_t> r = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(lead.raw)) + 1;
-        gptr<const uint32_t> g = (gptr<const uint32_t>)(reinterpret_cast<const uint32_t *>(jit.poly));
-        uint32_t *out = reinterpret_cast<uint32_t *>(jit.out);
-        const uint32_t D = lead.nbits, M = lead.m, rlen = lead.nbits + lead.m;
-        for (uint32_t m0 = 0; m0 < M; m0 += JUMP_MT) {
-            const uint32_t mt = (M - m0) < (uint32_t)JUMP_MT ? (M - m0) : (uint32_t)JUMP_MT;
-            switch ((mt + 255) / 256) {
-#define MTGP_JP(JA) \
-    case JA: jump_pass<JA>(r, g, out, active, D, rlen, m0, mt, planes, lane); break;
-                MTGP_JP(1) MTGP_JP(2)
-#undef MTGP_JP
-                default: break;
-            }
+    for (uint32_t blk = blockIdx.x; blk < n_blocks; blk += gridDim.x)
+        jump_block(items, n_items, blk, planes, wave, lane);
+}
+
+// Waits (a whole wave, every lane reading the same flag) until *flag is
+// nonzero; gives up after a bound far above any legitimate wait, counting
+// the give-up in *timeouts (the repair count: a jump evaluated too early
+// fails its segment check, and the request is regenerated).  The flag value
+// is made wave-uniform so that the loop exit is uniform.
+__device__ __forceinline__ void wait_flag(const uint32_t *flag, uint32_t *timeouts,
+                                          uint32_t lane) {
+    for (uint32_t spins = 0;; ++spins) {
+        const uint32_t f = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (f != 0u) break;
+        if (spins > (1u << 24)) {  // seconds of s_sleep
+            atomicAdd(timeouts, lane == 0 ? 1u : 0u);
+            break;
         }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// Prefix items and jump blocks of a batch in one persistent launch.  Every
+// wave first claims prefix items (one wave each, RAW: they dump the words
+// the jumps read); once the prefix counter is exhausted (every prefix has
+// been claimed by a running wave) the workgroup claims jump blocks, each of
+// which waits for its stream's prefix flag.  A jump block waits only on a
+// prefix claimed before any block, so every wait ends.
+struct PJArgs {
+    const uint32_t *params;
+    const BatchItem *prefix;  // nP prefix items
+    uint32_t nP;
+    const JumpItem *jumps;    // nJ jump items in blocks of JUMP_WAVES
+    uint32_t nJ;
+    const uint32_t *jdep;     // per block: index of its stream's prefix item
+    uint32_t *pflag;          // per prefix item: set to 1 when its words are stored
+    uint32_t *hdr;            // workspace header (claim counters, timeouts)
+    uint32_t win_below;
+};
+
+constexpr int PJ_LDS_BYTES = JUMP_LDS_BYTES + 16;  // planes + claim word
+
+template <int N>
+__global__ void __launch_bounds__(64 * JUMP_WAVES) pj_kernel(PJArgs a) {
+    using C = Core<N, 64, 4>;
+    static_assert(JUMP_WAVES * C::LDS_WORDS * 4 <= JUMP_LDS_BYTES, "prefix buffers fit the planes");
+    // No static LDS: the planes are read with 16-byte LDS loads, and a
+    // static word would move the dynamic region to offset 4.  The claim
+    // broadcast word sits right after the planes.
+    extern __shared__ uint32_t lds[];
+    uint32_t &s_claim = lds[JUMP_LDS_BYTES / 4];
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t *buf = lds + wave * C::LDS_WORDS;
+    while (true) {  // prefix items, one per wave
+        uint32_t v = 0;
+        if (lane == 0) v = atomicAdd(a.hdr + 0, 1u);
+        const uint32_t it = __builtin_amdgcn_readfirstlane(v);
+        if (it >= a.nP) break;
+        const BatchItem item = a.prefix[it];
+        const uint32_t *prm = a.params + (uint64_t)item.stream * P_WORDS;
+        if (item.mode & MODE_F32)
+            C::template run<true, true>(prm, item, buf, lane, nullptr, a.win_below);
+        else
+            C::template run<false, true>(prm, item, buf, lane, nullptr, a.win_below);
+        // every lane stores the flag: a lane-0-only store here lets the
+        // compiler split the claim loop by lane
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(a.pflag + it, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t n_blocks = (a.nJ + JUMP_WAVES - 1) / JUMP_WAVES;
+    __syncthreads();  // every wave of this workgroup is done with its prefix buffer
+    for (uint32_t t = threadIdx.x; t < (uint32_t)JUMP_PL; t += 64 * JUMP_WAVES) lds[t] = 0u;
+    while (true) {  // jump blocks, one per workgroup
+        __syncthreads();
+        if (threadIdx.x == 0) s_claim = atomicAdd(a.hdr + HDR_J_CLAIM, 1u);
+        __syncthreads();
+        const uint32_t blk = __builtin_amdgcn_readfirstlane(s_claim);
+        if (blk >= n_blocks) break;
+        if (wave == 0) wait_flag(a.pflag + a.jdep[blk], a.hdr + HDR_ERR, lane);
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        jump_block(a.jumps, a.nJ, blk, lds, wave, lane);
+    }
+}
+
+template <int N>
+static hipError_t launch_pj_n(const PJArgs &a, int num_cus, hipStream_t s) {
+    static bool attr_set = false;  // benign race: idempotent attribute
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)pj_kernel<N>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           PJ_LDS_BYTES);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const uint32_t work = a.nP + (a.nJ + JUMP_WAVES - 1) / JUMP_WAVES;
+    int grid = (int)(work > 0 ? work : 1);
+    const int cap = num_cus * 3;  // three workgroups of 48 KB fit a CU's LDS
+    if (grid > cap) grid = cap;
+    (void)hipGetLastError();  // report this launch only
+    hipLaunchKernelGGL(pj_kernel<N>, dim3(grid), dim3(64 * JUMP_WAVES), PJ_LDS_BYTES, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_jumps(int n_words, const BatchItem *prefix, uint32_t nP,
+                               const JumpItem *jumps, uint32_t nJ, const uint32_t *jdep,
+                               uint32_t *pflag, const uint32_t *params, uint32_t *hdr,
+                               uint32_t win_below, int num_cus, hipStream_t s) {
+    PJArgs a{params, prefix, nP, jumps, nJ, jdep, pflag, hdr, win_below};
+    switch (n_words) {
+        case 101: return launch_pj_n<101>(a, num_cus, s);
+        case 351: return launch_pj_n<351>(a, num_cus, s);
+        case 726: return launch_pj_n<726>(a, num_cus, s);
+        case 1391: return launch_pj_n<1391>(a, num_cus, s);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -817,7 +940,8 @@ __global__ void header_kernel(uint32_t *hdr, uint32_t tag_lo, uint32_t tag_hi,
     const uint32_t i = threadIdx.x;
     const bool fresh = hdr[HDR_TAG] != tag_lo || hdr[HDR_TAG + 1] != tag_hi;
     __builtin_amdgcn_wave_barrier();
-    const bool claim = i < (uint32_t)HDR_ERR || i == (uint32_t)HDR_FIX_CLAIM;
+    const bool claim = i < (uint32_t)HDR_ERR || i == (uint32_t)HDR_FIX_CLAIM ||
+                       i == (uint32_t)HDR_J_CLAIM;
     const bool errw = i >= (uint32_t)HDR_ERR && i < (uint32_t)(HDR_ERR + HDR_ERR_WORDS);
     const bool stamp = i >= HDR_STAMP_BYTE / 4 && i < HDR_STAMP_BYTE / 4 + 8;
     if (claim || (errw && (fresh || clear_errors)) || (stamp && fresh)) hdr[i] = 0u;

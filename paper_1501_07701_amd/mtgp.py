@@ -279,8 +279,9 @@ def set_phase_timing(enable: bool) -> None:
 
 
 def batch_phase_times(d_workspace, stream=None):
-    """(prefix, jumps, segments) durations in microseconds of the last batch
-    call on the workspace that ran with phase timing enabled."""
+    """(prefix-and-jump launch, segments, request checks) durations in
+    microseconds of the last batch call on the workspace that ran with phase
+    timing enabled."""
     us = (ctypes.c_double * 3)()
     _check(lib().mtgp_batch_phase_times(_ptr(d_workspace), _stream(stream), us),
            "mtgp_batch_phase_times")
