@@ -17,11 +17,13 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(BUILD, "libmtgp.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# HIP sources go through hipcc; mtgp_poly.cpp is plain host C++ built with
-# the host compiler and the carry-less multiply extension.
+# HIP sources go through hipcc; mtgp_poly.cpp (GF(2)[x] arithmetic, with the
+# carry-less multiply extension) and mtgp_sched.cpp (the serving scheduler)
+# are plain host C++ built with the host compiler.
 SOURCES = ["mtgp_kernels.hip", "mtgp_api.cpp", "mtgp_batch.cpp", "mtgp_server.cpp"]
-HOST_SOURCES = ["mtgp_poly.cpp"]
-HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-mpclmul", "-I", CSRC]
+HOST_SOURCES = ["mtgp_poly.cpp", "mtgp_sched.cpp"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-mpclmul", "-I", CSRC,
+              "-I", os.path.join(ROOT, "include")]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Wall", "-Wno-unused-command-line-argument",
