@@ -505,6 +505,12 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs) {
     return L;
 }
 
+WsState::~WsState() {
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (aux) (void)hipStreamDestroy(aux);
+}
+
 // Pinned staging for the uploaded plan: acquire waits until every upload
 // from this buffer has been consumed, then hands out at least n bytes; the
 // plan is written in place and stage_copy uploads a byte range of it.
@@ -612,6 +618,14 @@ static uint64_t header_tag(const void *d_ws) {
 
 // Launches the phases of the workspace's planned batch on `s`: header,
 // prefix items and jump evaluation (one launch), segments, request checks.
+// With w.overlap the whole (unsplit) requests, which need nothing from the
+// prefix and jump launch, run beside it and the segments: a launch on w.aux,
+// capped at w.overlap_groups workgroups per CU so that the prefix and jump
+// workgroups keep most of the chip, takes them; the segment launch follows
+// the prefix and jump launch on `s` at the CUs' full occupancy (its
+// workgroups beyond what is free start as the whole-request launch ends).
+// No launch waits for another's results, so the streams may run in any
+// order.
 static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, const WsState &w,
                          const mtgp_tuning &t, hipStream_t s, bool stamps, bool clear_errors) {
     uint32_t *hdr = (uint32_t *)ws;
@@ -632,6 +646,23 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
     a.persistent = true;
     a.num_cus = device_cus();
     a.stream = s;
+    const BatchItem *C = (const BatchItem *)(ws + w.off_C);
+    const bool fork = w.overlap && (w.nA || w.nB) && w.nCs < w.nC && w.aux;
+    if (fork) {
+        if ((e = hipEventRecord(w.ev_fork, s)) != hipSuccess)
+            return hip_fail(e, "hipEventRecord(fork)");
+        if ((e = hipStreamWaitEvent(w.aux, w.ev_fork, 0)) != hipSuccess)
+            return hip_fail(e, "hipStreamWaitEvent(fork)");
+        LaunchArgs a1 = a;
+        a1.stream = w.aux;
+        a1.items = C + w.nCs;
+        a1.n_items = w.nC - w.nCs;
+        a1.counter = hdr + HDR_W_CLAIM;
+        a1.groups_per_cu = w.overlap_groups;
+        if ((rc = launch_tuned(ps.N, t, a1))) return rc;
+        if ((e = hipEventRecord(w.ev_join, w.aux)) != hipSuccess)
+            return hip_fail(e, "hipEventRecord(join)");
+    }
     if (w.nA || w.nB) {  // prefix items and jump blocks, one launch
         if ((e = launch_prefix_jumps(ps.N, (const BatchItem *)(ws + w.off_A), w.nA,
                                      (const JumpItem *)(ws + w.off_B), w.nB,
@@ -642,10 +673,12 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
             return hip_fail(e, "prefix and jump kernel");
     }
     if ((rc = stamp(1))) return rc;
-    a.items = (const BatchItem *)(ws + w.off_C);
-    a.n_items = w.nC;
+    a.items = C;
     a.counter = hdr + 1;
+    a.n_items = fork ? w.nCs : w.nC;
     if ((rc = launch_tuned(ps.N, t, a))) return rc;
+    if (fork && (e = hipStreamWaitEvent(s, w.ev_join, 0)) != hipSuccess)
+        return hip_fail(e, "hipStreamWaitEvent(join)");
     if ((rc = stamp(2))) return rc;
     if (w.nF) {  // request checks of the split requests
         a.items = (const BatchItem *)(ws + w.off_F);
@@ -662,7 +695,7 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
 static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
                       uint32_t *d_states, int stride, const std::vector<Request> &reqs,
                       char *ws, size_t ws_bytes, hipStream_t s, const mtgp_tuning &t,
-                      WsState &w) {
+                      WsState &w, bool overlap) {
     const int N = ps->N;
     std::vector<Seg> segs(reqs.size());
     std::vector<int> want;
@@ -724,7 +757,15 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         return rc;
     }
     auto at = [&](size_t off) { return img + off; };
-    std::vector<std::pair<uint64_t, BatchItem>> C;
+    // segment items: steps, item, and for segments of split requests the
+    // split index and segment number (their start state's producer)
+    struct CItem {
+        uint64_t steps;
+        BatchItem b;
+        int ri;  // -1: a whole request
+        int k;
+    };
+    std::vector<CItem> C;
     std::vector<std::tuple<uint64_t, BatchItem, size_t>> A;  // steps, item, split index
     std::vector<std::vector<JumpItem>> Bs;                   // per split request, padded
     std::vector<BatchItem> F;
@@ -749,7 +790,7 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
             BatchItem b = base_item(r.count, 0);
             b.state_in = b.state_out = (uint64_t)(uintptr_t)row;
             b.flag = r.flag;
-            C.emplace_back((r.count + so - 1) / so, b);
+            C.push_back(CItem{(r.count + so - 1) / so, b, -1, 0});
             continue;
         }
         // request record and check item of a split request
@@ -820,13 +861,11 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
             } else {
                 b.state_out = (uint64_t)(uintptr_t)row;
             }
-            C.emplace_back((end - start + so - 1) / so, b);
+            C.push_back(CItem{(end - start + so - 1) / so, b, (int)ri, k});
         }
     }
-    auto lpt = [](const auto &x, const auto &y) { return x.first > y.first; };
     std::stable_sort(A.begin(), A.end(),
                      [](const auto &x, const auto &y) { return std::get<0>(x) > std::get<0>(y); });
-    std::stable_sort(C.begin(), C.end(), lpt);
     // prefixes longest first; jump blocks of the streams with the shortest
     // prefixes first (their words are ready soonest), each block naming its
     // stream's prefix item
@@ -842,8 +881,24 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
             ((uint32_t *)at(L.off_jdep))[nb] = (uint32_t)i;
         }
     }
-    for (size_t i = 0; i < C.size(); ++i)
-        std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].second, sizeof(BatchItem));
+    // Segment list, longest first.  Overlapped (whole requests beside the
+    // prefix and jump launch): the segments of split requests first, then
+    // the whole requests, each part longest first.  Only where the whole
+    // requests are at most half the segments' steps, so that their launch,
+    // capped below the chip's occupancy, does not outlast the segments.
+    uint64_t whole_steps = 0, seg_steps = 0;
+    for (const CItem &c : C) (c.ri < 0 ? whole_steps : seg_steps) += c.steps;
+    const bool split_lists =
+        overlap && !A.empty() && whole_steps > 0 && 2 * whole_steps <= seg_steps;
+    std::stable_sort(C.begin(), C.end(), [&](const CItem &x, const CItem &y) {
+        if (split_lists && (x.ri < 0) != (y.ri < 0)) return x.ri >= 0;
+        return x.steps > y.steps;
+    });
+    size_t n_seg = 0;
+    for (size_t i = 0; i < C.size(); ++i) {
+        std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].b, sizeof(BatchItem));
+        if (C[i].ri >= 0) ++n_seg;
+    }
     if (!F.empty()) std::memcpy(at(L.off_F), F.data(), F.size() * sizeof(BatchItem));
     w.nA = (uint32_t)A.size();
     w.nB = (uint32_t)(nb * JUMP_BLOCK);
@@ -855,6 +910,8 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
     w.off_F = L.off_F;
     w.off_jdep = L.off_jdep;
     w.off_pflag = L.off_pflag;
+    w.nCs = (uint32_t)(split_lists ? n_seg : C.size());
+    w.overlap = split_lists;
     w.tables_end = L.off_poly;
     w.up_end = L.up_end;
     w.ps = ps;
@@ -862,13 +919,59 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
     return MTGP_OK;
 }
 
+// Workgroups per CU of the first (concurrent) segment launch in overlapped
+// mode, 0 = do not overlap.  At most half the launch variant's occupancy,
+// and only where that leaves LDS for a prefix-and-jump workgroup on every
+// CU.  MTGP_OVERLAP=0 turns overlapping off; MTGP_OVERLAP=k asks for k.
+static int overlap_groups(const ParamSet &ps, const mtgp_tuning &t) {
+    const char *v = getenv("MTGP_OVERLAP");
+    if (v && v[0] == '0') return 0;
+    const int wpb = t.threads_per_stream == 64 ? t.workgroup_size / 64 : 1;
+    const int slots = variant_slots_per_cu(ps.N, t.threads_per_stream, t.outputs_per_lane, wpb);
+    const int per_cu = t.threads_per_stream == 64 ? slots / wpb : slots;
+    if (per_cu < 2) return 0;
+    int g = per_cu / 2;
+    if (v && v[0] >= '1' && v[0] <= '9') g = std::min(per_cu - 1, atoi(v));
+    size_t wg_lds = 0;
+    VariantInfo vi[64];
+    const int nv = variant_count(ps.N, vi, 64);
+    for (int i = 0; i < nv; ++i)
+        if (vi[i].tps == t.threads_per_stream && vi[i].k == t.outputs_per_lane &&
+            vi[i].wpb == wpb)
+            wg_lds = vi[i].lds_bytes;
+    int dev = 0, lds_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+            hipSuccess)
+        return 0;
+    if (!wg_lds || (size_t)g * wg_lds + prefix_jump_lds_bytes() > (size_t)lds_cu) return 0;
+    return g;
+}
+
 int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
               int stride, const std::vector<Request> &reqs, void *d_ws, size_t ws_bytes,
               hipStream_t s, const mtgp_tuning &t, bool use_graph, WsState &w,
-              bool per_call_errors) {
+              bool per_call_errors, bool allow_overlap) {
     if (reqs.empty()) return MTGP_OK;
     char *ws = (char *)d_ws;
     hipError_t e;
+    const bool stamps = g_stamps.load();
+    int ov = 0;
+    if (allow_overlap && !w.no_alloc && !stamps) {
+        hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cst) == hipSuccess && cst == hipStreamCaptureStatusNone)
+            ov = overlap_groups(*ps, t);
+    }
+    if (ov && !w.aux) {
+        if ((e = hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking)) != hipSuccess) {
+            w.aux = nullptr;
+            return hip_fail(e, "hipStreamCreate(overlap)");
+        }
+        if ((e = hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate(overlap)");
+    }
+    w.overlap_groups = ov;
     uint64_t sig = mix(0x51ull, (uint64_t)(uintptr_t)d_params);
     sig = mix(sig, ps->generation);
     sig = mix(sig, (uint64_t)(uintptr_t)d_states);
@@ -877,6 +980,7 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
     sig = mix(sig, ((uint64_t)t.threads_per_stream << 48) ^ ((uint64_t)t.outputs_per_lane << 32) ^
                        ((uint64_t)t.workgroup_size << 16) ^ (uint64_t)(uint32_t)t.jump_target_steps);
     sig = mix(sig, (uint64_t)(uint32_t)t.window_below_w);
+    sig = mix(sig, ov ? 2u : 1u);  // overlapped plans order their segment list differently
     for (const Request &r : reqs) {
         sig = mix(sig, ((uint64_t)(uint32_t)r.stream << 32) | r.dtype);
         sig = mix(sig, r.count);
@@ -902,15 +1006,15 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         if (rc) return rc;
     } else {
         w.sig = 0;
-        int rc = build_plan(ps, d_params, d_states, stride, reqs, ws, ws_bytes, s, t, w);
+        int rc = build_plan(ps, d_params, d_states, stride, reqs, ws, ws_bytes, s, t, w, ov > 0);
         if (rc) return rc;
         rc = stage_copy(w, HDR_BYTES, w.up_end, ws, s);
         if (rc) return rc;
         w.sig = sig;
     }
 
-    const bool stamps = g_stamps.load();
-    if (!use_graph || !graphs_enabled())
+    // overlapped calls launch directly (two streams, not a captured graph)
+    if (!use_graph || !graphs_enabled() || w.overlap)
         return launch_phases(*ps, d_params, ws, w, t, s, stamps, per_call_errors);
 
     int dev = 0;
@@ -1004,7 +1108,7 @@ static int batch_common(const void *d_params, uint32_t *d_states, int stride,
     WsState &w = own ? *own : *held;
     std::lock_guard<std::mutex> lk(w.mu);
     return run_batch(ps, d_params, d_states, stride, to_requests(h_items, n_items), d_ws,
-                     ws_bytes, s, t, use_graph, w, false);
+                     ws_bytes, s, t, use_graph, w, false, true);
 }
 
 }  // namespace mtgp
@@ -1129,7 +1233,7 @@ int mtgp_generate_batch_noalloc(const void *d_params, uint32_t *d_states, int st
     std::lock_guard<std::mutex> lk(w->mu);
     return run_batch(ps, d_params, d_states, state_stride, to_requests(h_items, n_items), scr,
                      (size_t)MTGP_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream,
-                     tuning_for(ps->N), false, *w, false);
+                     tuning_for(ps->N), false, *w, false, false);
 }
 
 int mtgp_set_phase_timing(int enable) {

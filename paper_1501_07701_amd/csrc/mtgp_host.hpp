@@ -62,6 +62,14 @@ struct WsState {
     uint64_t sig = 0;          // plan signature, 0 = no plan
     uint32_t nA = 0, nB = 0, nC = 0, nF = 0;  // prefix, jump, segment, check items
     size_t off_A = 0, off_B = 0, off_C = 0, off_F = 0, off_jdep = 0, off_pflag = 0;
+    // overlap: the plan's whole requests (after the nCs segments of split
+    // requests in the segment list) start on `aux` beside the prefix and
+    // jump launch, with at most overlap_groups workgroups per CU
+    uint32_t nCs = 0;
+    bool overlap = false;
+    int overlap_groups = 0;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     size_t tables_end = 0, up_end = 0;
     std::weak_ptr<ParamSet> ps;         // parameter set of the last plan
     std::vector<int32_t> split_streams;  // streams the last plan split
@@ -70,6 +78,7 @@ struct WsState {
     // pinned memory, and no jump-ahead data is built
     bool no_alloc = false;
     std::vector<uint8_t> image;
+    ~WsState();
 };
 
 int fail(int code, const char *fmt, ...);
@@ -96,10 +105,13 @@ struct Request {
 // jump-ahead segments as far as ws_bytes allows.  The caller holds wst.mu.
 // per_call_errors zeroes the workspace's repair count and log at the start
 // of the call (else they accumulate until mtgp_batch_errors reads them).
+// allow_overlap: whole requests may start beside the prefix and jump launch
+// (on a second stream the workspace state owns; not while `s` is being
+// captured, with phase timing on, or for no_alloc workspaces).
 int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_t *d_states,
               int stride, const std::vector<Request> &reqs, void *d_ws, size_t ws_bytes,
               hipStream_t s, const mtgp_tuning &t, bool use_graph, WsState &wst,
-              bool per_call_errors);
+              bool per_call_errors, bool allow_overlap);
 // Streams named in a workspace header's repair log (all streams the plan
 // split when the log overflowed) are marked dirty so that their jump-ahead
 // polynomial is rebuilt from their current state.

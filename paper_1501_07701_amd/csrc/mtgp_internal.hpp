@@ -91,12 +91,15 @@ static_assert(sizeof(BatchItem) == 80, "BatchItem layout");
 //   word 15     claim counter of the jump blocks
 //   byte 64..95 phase timestamps (64-bit: start, after the prefix and
 //               jump launch, after the segments, end)
+//   word 24     claim counter of the whole-request list when it runs beside
+//               the prefix and jump launch
 constexpr int HDR_ERR = 2;
 constexpr int HDR_LOG_MAX = 8;
 constexpr int HDR_ERR_WORDS = 2 + HDR_LOG_MAX;  // words HDR_ERR .. HDR_ERR + 9
 constexpr int HDR_FIX_CLAIM = 12;
 constexpr int HDR_TAG = 13;
 constexpr int HDR_J_CLAIM = 15;
+constexpr int HDR_W_CLAIM = 24;
 constexpr size_t HDR_STAMP_BYTE = 64;
 constexpr size_t HDR_BYTES = 256;
 
@@ -127,6 +130,7 @@ struct LaunchArgs {
     uint32_t *counter;
     uint32_t *err;           // header word HDR_ERR (repair count, then the log)
     uint32_t win_below;      // window path for eligible streams with W below this
+    int groups_per_cu;       // persistent launches: at most this many groups per CU (0 = occupancy)
     bool persistent;
     int num_cus;
     void *stream;
@@ -145,6 +149,8 @@ hipError_t launch_jump(const JumpItem *items, uint32_t n_items, int num_cus, hip
 // of the request-check kernel (MODE_FIXUP items) for state length n_words
 // (one wave per item; a.win_below applies).
 hipError_t launch_prefix(int n_words, const LaunchArgs &a);
+// LDS bytes of one prefix-and-jump workgroup.
+size_t prefix_jump_lds_bytes();
 // Prefix items (nP, one wave each) and jump blocks (nJ items in blocks of
 // JUMP_BLOCK; block b waits for pflag[jdep[b]]) in one persistent launch.
 hipError_t launch_prefix_jumps(int n_words, const BatchItem *prefix, uint32_t nP,

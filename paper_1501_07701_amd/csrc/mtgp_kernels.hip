@@ -910,6 +910,8 @@ hipError_t launch_prefix_jumps(int n_words, const BatchItem *prefix, uint32_t nP
     }
 }
 
+size_t prefix_jump_lds_bytes() { return PJ_LDS_BYTES; }
+
 // Seeding: one lane per stream runs the N-step initialisation recurrence.
 __global__ void seed_kernel(const uint32_t *__restrict__ params,
                             uint32_t *__restrict__ states, uint32_t stride,
@@ -941,7 +943,7 @@ __global__ void header_kernel(uint32_t *hdr, uint32_t tag_lo, uint32_t tag_hi,
     const bool fresh = hdr[HDR_TAG] != tag_lo || hdr[HDR_TAG + 1] != tag_hi;
     __builtin_amdgcn_wave_barrier();
     const bool claim = i < (uint32_t)HDR_ERR || i == (uint32_t)HDR_FIX_CLAIM ||
-                       i == (uint32_t)HDR_J_CLAIM;
+                       i == (uint32_t)HDR_J_CLAIM || i == (uint32_t)HDR_W_CLAIM;
     const bool errw = i >= (uint32_t)HDR_ERR && i < (uint32_t)(HDR_ERR + HDR_ERR_WORDS);
     const bool stamp = i >= HDR_STAMP_BYTE / 4 && i < HDR_STAMP_BYTE / 4 + 8;
     if (claim || (errw && (fresh || clear_errors)) || (stamp && fresh)) hdr[i] = 0u;
@@ -996,6 +998,7 @@ static hipError_t launch_with(GenFn fn, bool *attr_set, const LaunchArgs &a) {
         int per_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds);
         if (e != hipSuccess) return e;
+        if (a.groups_per_cu > 0 && a.groups_per_cu < per_cu) per_cu = a.groups_per_cu;
         if (per_cu < 1) per_cu = 1;
         if (per_cu * a.num_cus < grid) grid = per_cu * a.num_cus;
     }

@@ -81,7 +81,7 @@ class HipBackend final : public SchedBackend {
         }
         std::lock_guard<std::mutex> sg(sl.wst->mu);
         int rc = run_batch(ps, d_params, d_states, stride, work, sl.d_ws, ws_bytes, sl.hs,
-                           tuning_for(ps->N), false, *sl.wst, true);
+                           tuning_for(ps->N), false, *sl.wst, true, false);
         if (rc == MTGP_OK) {
             // the batch's repair count and log come back with the slot
             hipError_t e = hipMemcpyAsync(sl.h_err, (uint32_t *)sl.d_ws + HDR_ERR,
