@@ -962,6 +962,15 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         if (hipStreamIsCapturing(s, &cst) == hipSuccess && cst == hipStreamCaptureStatusNone)
             ov = overlap_groups(*ps, t);
     }
+    if (ov) {
+        // only a batch with both split and whole requests overlaps; for the
+        // others the plan is the same either way, and phase-timed calls keep
+        // using the cached one
+        const uint64_t T = effective_target(*ps, reqs, t);
+        bool any_split = false, any_whole = false;
+        for (const Request &r : reqs) (wants_split(*ps, r, T, t) ? any_split : any_whole) = true;
+        if (!(any_split && any_whole)) ov = 0;
+    }
     if (ov && !w.aux) {
         if ((e = hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking)) != hipSuccess) {
             w.aux = nullptr;
