@@ -263,3 +263,49 @@ def test_states_written_behind_the_library_are_repaired(torch):
         assert repairs[0] >= 1, repairs            # the checks caught the wrong orbits
         assert repairs[1] == 0, repairs            # rebuilt from the current states
         g.close()
+
+
+@pytest.mark.parametrize("overlap", ["0", "default"])
+def test_whole_requests_beside_the_jumps(torch, overlap):
+    """A batch with long (split) and short (whole) requests: by default the
+    whole requests run on a second stream beside the prefix and jump launch
+    (MTGP_OVERLAP=0 runs the phases one after another).  Both give the
+    oracle's outputs and final states, over two calls in a row."""
+    import os
+    _say("case whole requests beside the jumps, MTGP_OVERLAP=%s" % overlap)
+    mexp = 11213
+    N = mexp // 32 + 1
+    n_long, n_short = 6, 26
+    p = workloads.make_params(mexp, n_long + n_short, 0x0E71)
+    p[0, 1] = N - 2                                   # a W = 2 stream among the long ones
+    seeds = np.arange(1, n_long + n_short + 1, dtype=np.uint32)
+    counts = [200000 + 1111 * k for k in range(n_long)] + [3000 + 97 * k for k in range(n_short)]
+    dts = [k % 2 for k in range(n_long + n_short)]
+    old = os.environ.get("MTGP_OVERLAP")
+    if overlap == "0":
+        os.environ["MTGP_OVERLAP"] = "0"
+    else:
+        os.environ.pop("MTGP_OVERLAP", None)
+    try:
+        with _Tune(mexp, 256):
+            g = mtgp.Generators(p, seeds)
+            outs = [torch.empty(c, dtype=torch.int32, device="cuda") for c in counts]
+            items = [(k, dts[k], counts[k], outs[k]) for k in range(len(counts))]
+            assert mtgp.batch_workspace_query(g.d_params, items) > \
+                mtgp.batch_workspace_bytes(len(items))    # the long ones split
+            ws = g.workspace(items)
+            states = [oracle.seed(int(seeds[k]), N) for k in range(len(counts))]
+            for rep in range(2):
+                g.batch(items, ws)
+                got = [_host(o).copy() for o in outs]
+                assert mtgp.batch_errors(ws) == 0
+                for k in range(len(counts)):
+                    o, states[k] = oracle.generate(p[k], states[k], counts[k], bool(dts[k]))
+                    assert np.array_equal(got[k], np.asarray(o).view(np.uint32)), (rep, k)
+            assert np.array_equal(g.states_host(), np.array(states))
+            g.close()
+    finally:
+        if old is None:
+            os.environ.pop("MTGP_OVERLAP", None)
+        else:
+            os.environ["MTGP_OVERLAP"] = old
