@@ -7,7 +7,8 @@ its seed status on the device, generate 2^24 uint32 outputs per stream,
 re-seed, generate 2^24 float32 outputs per stream from the same initial
 states (both passes through the persistent batch kernel replayed from a
 hipGraph).  Inputs (parameter blocks, seeds) are resident in HBM before
-timing starts.
+timing starts.  The default line also carries compact figures of the C3
+and C4 batches and of a shortened C5 serving sweep (--no-extras drops them).
 
 --workload selects the scheduler and serving measurements instead:
   C3  4096 mexp-23209 streams x 2^20 uint32 in one autotuned graph launch
@@ -484,13 +485,15 @@ def run_c4(args):
         finally:
             mtgp.set_tuning(mexp, *tt)
 
-    log("one launch per stream, jump-ahead on ...")
-    b_split = per_stream(True)
-    log("one launch per stream, jump-ahead off ...")
-    b_plain = per_stream(False)
-    if b_split[2] or b_plain[2]:
-        log("jump-ahead segment checks failed in the per-stream runs")
-        sys.exit(3)
+    baselines = getattr(args, "c4_baselines", True)
+    if baselines:
+        log("one launch per stream, jump-ahead on ...")
+        b_split = per_stream(True)
+        log("one launch per stream, jump-ahead off ...")
+        b_plain = per_stream(False)
+        if b_split[2] or b_plain[2]:
+            log("jump-ahead segment checks failed in the per-stream runs")
+            sys.exit(3)
     fill = _fill_gbps(torch, mtgp, out, stream)
     alg = total * 4 + n * (8 * N + 256)
     cpu = None
@@ -518,7 +521,8 @@ def run_c4(args):
                         "jump_ahead_ms": round(b_split[0], 2),
                         "unsplit_ms": round(b_plain[0], 2),
                         "speedup_of_batch_vs_jump_ahead": round(b_split[0] / ms_step, 2),
-                        "speedup_of_batch_vs_unsplit": round(b_plain[0] / ms_step, 2)}})
+                        "speedup_of_batch_vs_unsplit": round(b_plain[0] / ms_step, 2)}
+                    if baselines else None})
 
 
 def run_paper(args):
@@ -800,7 +804,7 @@ def run_c5(args):
     return line
 
 
-def _compact_c3(line):
+def _compact(line):
     keys = ("value", "unit", "ms_per_step", "avg_generate_launch_ms", "roofline",
             "phases_us_prefixjumps_segments_checks", "segment_phase_GBps", "store_only_fill_GBps",
             "autotuned", "min_step_width", "config")
@@ -827,7 +831,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="default workload only: skip the C3 and C5 figures added "
+                    help="default workload only: skip the C3, C4 and C5 figures added "
                          "to the line (profiling runs)")
     ap.add_argument("--extra-requests", type=int, default=4000,
                     help="requests per replay in the C5 figures of the default line")
@@ -849,13 +853,18 @@ def main():
     line = run(args)
     if args.workload == "C2" and not args.no_extras:
         # the scheduler and serving rows in the same run: the autotuned
-        # C3 batch (one graph launch) and a shortened C5 sweep
+        # C3 batch (one graph launch), the autotuned uneven C4 batch and a
+        # shortened C5 sweep
         torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(args))
         sub.no_cpu_baseline = True
         sub.steps, sub.warmup = min(args.steps, 10), min(args.warmup, 2)
         log("C3 (autotuned batch) ...")
-        line["C3"] = _compact_c3(run_c3(sub))
+        line["C3"] = _compact(run_c3(sub))
+        torch.cuda.empty_cache()
+        log("C4 (autotuned uneven batch) ...")
+        sub.c4_baselines = False  # the one-launch-per-stream runs: --workload C4
+        line["C4"] = _compact(run_c4(sub))
         torch.cuda.empty_cache()
         line["C5"] = serve_c5(sub, args.extra_requests, (0.5, 1.0), (0.5, 2.0))
     print(json.dumps(line), flush=True)
