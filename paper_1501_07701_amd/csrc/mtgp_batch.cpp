@@ -475,6 +475,11 @@ static bool wants_split(const ParamSet &ps, const Request &r, uint64_t T, const 
     return (r.count + so - 1) / so > T && r.count > (uint64_t)ps.mexp + 128;
 }
 
+// Jump items per jump: one per JUMP_OUT_WORDS words of the N-word state.
+static size_t jump_passes(int N) {
+    return ((size_t)N + JUMP_OUT_WORDS - 1) / JUMP_OUT_WORDS;
+}
+
 static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs) {
     size_t nA = 0, nB = 0, nC = 0, poly_words = 0, raw_words = 0, js_words = 0;
     for (const Seg &g : segs) {
@@ -483,7 +488,7 @@ static Layout layout_for(const ParamSet &ps, const std::vector<Seg> &segs) {
             continue;
         }
         ++nA;
-        nB += ((size_t)g.C - 1 + JUMP_BLOCK - 1) / JUMP_BLOCK * JUMP_BLOCK;
+        nB += ((size_t)g.C - 1 + JUMP_BLOCK - 1) / JUMP_BLOCK * JUMP_BLOCK * jump_passes(ps.N);
         nC += (size_t)g.C;
         poly_words += ((size_t)g.C - 1) * (((size_t)g.Dsize + 31) / 32);
         raw_words += ((size_t)ps.N + (size_t)g.Dsize + 1 + 63) / 64 * 64;
@@ -824,26 +829,35 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         a.raw = (uint64_t)(uintptr_t)raw;
         A.emplace_back((P + so - 1) / so, a, ri);
         // B: jumps, segment k >= 1 starts at output (c0+k-1)*lseg and
-        // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words
+        // its state is x^((c0+k-1)*lseg - 1) mod p applied to the words;
+        // each jump is evaluated in passes of JUMP_OUT_WORDS state words
+        // (blocks of JUMP_BLOCK jumps per pass), word m0 onwards reading the
+        // raw words from m0 on
         const size_t pw = ((size_t)D + 31) / 32;
         Bs.emplace_back();
         std::vector<JumpItem> &B = Bs.back();
+        std::vector<uint64_t> polys((size_t)g.C);
         for (int k = 1; k < g.C; ++k) {
             const uint64_t c = g.c0 + (uint64_t)k - 1;
-            JumpItem j;
-            j.raw = (uint64_t)(uintptr_t)raw;
-            j.poly = (uint64_t)(uintptr_t)(ws + poly_off);
-            j.out = (uint64_t)(uintptr_t)(js + (size_t)k * N);
-            j.nbits = (uint32_t)D;
-            j.m = (uint32_t)N;
+            polys[(size_t)k] = (uint64_t)(uintptr_t)(ws + poly_off);
             std::memcpy(at(poly_off), g.sj->g[(size_t)c - 1].data(), pw * 4);
             poly_off += pw * 4;
-            B.push_back(j);
         }
-        while (B.size() % JUMP_BLOCK) {  // pad this stream's block
-            JumpItem z;
-            std::memset(&z, 0, sizeof z);
-            B.push_back(z);
+        for (int m0 = 0; m0 < N; m0 += JUMP_OUT_WORDS) {
+            for (int k = 1; k < g.C; ++k) {
+                JumpItem j;
+                j.raw = (uint64_t)(uintptr_t)(raw + m0);
+                j.poly = polys[(size_t)k];
+                j.out = (uint64_t)(uintptr_t)(js + (size_t)k * N + (size_t)m0);
+                j.nbits = (uint32_t)D;
+                j.m = (uint32_t)std::min(JUMP_OUT_WORDS, N - m0);
+                B.push_back(j);
+            }
+            while (B.size() % JUMP_BLOCK) {  // pad this pass's last block
+                JumpItem z;
+                std::memset(&z, 0, sizeof z);
+                B.push_back(z);
+            }
         }
         // C: segments; every one but the last checks its end state against
         // the next one's jumped start

@@ -109,6 +109,12 @@ constexpr size_t HDR_BYTES = 256;
 // share raw, nbits and m (one stream); null items (out == 0) pad a block and
 // the first item of a block is never null.
 constexpr int JUMP_BLOCK = 4;
+// Output words one jump item evaluates in a single pass over its
+// coefficients; longer states are split into items of at most this many
+// words (item p covers words p * JUMP_OUT_WORDS onwards, its raw pointer
+// moved by as many words), so the passes of one jump run on different
+// workgroups at once.
+constexpr int JUMP_OUT_WORDS = 512;
 struct JumpItem {
     uint64_t raw;     // words x_0, x_1, ... of a stream (at least nbits + m + 1)
     uint64_t poly;    // coefficients g_0 .. g_{nbits-1}, 32 per uint32 word

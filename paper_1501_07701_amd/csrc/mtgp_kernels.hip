@@ -685,6 +685,7 @@ constexpr int JUMP_CH = 256;    // coefficients per chunk (multiple of 32)
 constexpr int JUMP_JA = 8;      // output words per lane per pass
 constexpr int JUMP_MT = 64 * JUMP_JA;
 constexpr int JUMP_PL = JUMP_CH + JUMP_MT;  // plane length (words)
+static_assert(JUMP_MT == JUMP_OUT_WORDS, "the planner splits jumps into passes of JUMP_MT words");
 constexpr int JUMP_LDS_BYTES = 16 * JUMP_PL * 4;
 
 typedef uint32_t jv4 __attribute__((ext_vector_type(4)));

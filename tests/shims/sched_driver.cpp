@@ -420,7 +420,11 @@ static void fusion_and_order() {
     B.hold_us = 0;
     const int dt[6] = {MTGP_U32, MTGP_U32, MTGP_U32, MTGP_F32, MTGP_F32, MTGP_U32};
     const uint64_t cnt[6] = {10, 20, 30, 40, 50, 60};
-    for (int i = 0; i < 6; ++i) CHECK(S.submit(0, cnt[i], dt[i], &t[i]) == MTGP_OK, "submit");
+    // one submission, so that admission sees all six queued (requests that
+    // arrive one by one may be admitted one by one: admission does not wait
+    // for a free launch slot)
+    const int32_t st0[6] = {0, 0, 0, 0, 0, 0};
+    CHECK(S.submit_many(st0, cnt, dt, 6, t) == MTGP_OK, "submit_many");
     for (int i = 0; i < 6; ++i) CHECK(S.wait(t[i], 0) == MTGP_OK, "wait %d", i);
     CHECK(S.wait(t0, 0) == MTGP_OK, "wait first");
     std::vector<Done> done;
