@@ -160,7 +160,12 @@ int mtgp_batch_workspace_query(const void *d_params, const mtgp_work *h_items,
  * uneven lengths and mixed dtypes in a single launch, replayed from a
  * hipGraph captured once per (buffers, plan, tuning).  Items are scheduled
  * longest-critical-path first.  A stream id may appear at most once per
- * call.
+ * call.  When a batch has both split (see below) and whole requests, the
+ * whole requests run beside the jump-ahead evaluation on a second HIP
+ * stream the library owns per workspace (joined back into `stream` before
+ * the call's last kernel; launched directly, not from a graph, and not
+ * while `stream` is being captured).  MTGP_OVERLAP=0 in the environment
+ * turns this off.
  *
  * Jump-ahead (not in the paper; the generator's GF(2)-linearity makes it
  * exact): a stream whose request needs more dependent steps than the
