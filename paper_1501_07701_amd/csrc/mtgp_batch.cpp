@@ -762,13 +762,12 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
         return rc;
     }
     auto at = [&](size_t off) { return img + off; };
-    // segment items: steps, item, and for segments of split requests the
-    // split index and segment number (their start state's producer)
+    // segment list entries: steps, item, and whether the item is a segment
+    // of a split request (else a whole request)
     struct CItem {
         uint64_t steps;
         BatchItem b;
-        int ri;  // -1: a whole request
-        int k;
+        bool segment;
     };
     std::vector<CItem> C;
     std::vector<std::tuple<uint64_t, BatchItem, size_t>> A;  // steps, item, split index
@@ -795,7 +794,7 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
             BatchItem b = base_item(r.count, 0);
             b.state_in = b.state_out = (uint64_t)(uintptr_t)row;
             b.flag = r.flag;
-            C.push_back(CItem{(r.count + so - 1) / so, b, -1, 0});
+            C.push_back(CItem{(r.count + so - 1) / so, b, false});
             continue;
         }
         // request record and check item of a split request
@@ -875,7 +874,7 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
             } else {
                 b.state_out = (uint64_t)(uintptr_t)row;
             }
-            C.push_back(CItem{(end - start + so - 1) / so, b, (int)ri, k});
+            C.push_back(CItem{(end - start + so - 1) / so, b, true});
         }
     }
     std::stable_sort(A.begin(), A.end(),
@@ -901,17 +900,17 @@ static int build_plan(const std::shared_ptr<ParamSet> &ps, const void *d_params,
     // requests are at most half the segments' steps, so that their launch,
     // capped below the chip's occupancy, does not outlast the segments.
     uint64_t whole_steps = 0, seg_steps = 0;
-    for (const CItem &c : C) (c.ri < 0 ? whole_steps : seg_steps) += c.steps;
+    for (const CItem &c : C) (c.segment ? seg_steps : whole_steps) += c.steps;
     const bool split_lists =
         overlap && !A.empty() && whole_steps > 0 && 2 * whole_steps <= seg_steps;
     std::stable_sort(C.begin(), C.end(), [&](const CItem &x, const CItem &y) {
-        if (split_lists && (x.ri < 0) != (y.ri < 0)) return x.ri >= 0;
+        if (split_lists && x.segment != y.segment) return x.segment;
         return x.steps > y.steps;
     });
     size_t n_seg = 0;
     for (size_t i = 0; i < C.size(); ++i) {
         std::memcpy(at(L.off_C) + i * sizeof(BatchItem), &C[i].b, sizeof(BatchItem));
-        if (C[i].ri >= 0) ++n_seg;
+        if (C[i].segment) ++n_seg;
     }
     if (!F.empty()) std::memcpy(at(L.off_F), F.data(), F.size() * sizeof(BatchItem));
     w.nA = (uint32_t)A.size();
