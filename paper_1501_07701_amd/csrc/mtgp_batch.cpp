@@ -9,8 +9,9 @@
 // state J+1 outputs ahead, x_{J+1} .. x_{J+N}, needs only x_1 .. x_{D+N}.
 // A split request therefore runs as
 //   A: a prefix item: the first P = D+1 outputs, also dumping x_0..x_{N+D};
-//   B: one jump item per later segment, which starts at output c*lseg
-//      (c >= c0 = ceil((P+1)/lseg)): its state from g_c = x^(c*lseg-1) mod p;
+//   B: one jump per later segment, which starts at output c*lseg
+//      (c >= c0 = ceil((P+1)/lseg)): its state from g_c = x^(c*lseg-1) mod p,
+//      evaluated as one item per 512 state words;
 //   C: every segment (the first one continues after the prefix up to
 //      c0*lseg), each checking its end state against the next segment's
 //      start state.
@@ -1022,8 +1023,8 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
                 }
     }
     if (w.sig == sig && !dirty && w.ps.lock() == ps) {
-        // same plan: the polynomials are in place; the item tables and
-        // request records (device pointers, countdowns) go up every call
+        // same plan: the polynomials are in place; the item tables,
+        // request records and prefix flags go up every call
         int rc = stage_copy(w, HDR_BYTES, w.tables_end, ws, s);
         if (rc) return rc;
     } else {
