@@ -399,6 +399,41 @@ def test_c4_full_size_every_stream(torch):
     g.close()
 
 
+@pytest.mark.parametrize("name", ["P1", "P2"])
+def test_paper_shapes_full_size_every_stream(torch, name):
+    """The paper's experiment shapes (mexp 3217, 2^20 uint32 per stream):
+    P1 10,000 statuses at seed status 0, P2 100 statuses x 100 seeds, in one
+    batch call as the benchmark runs them: every stream against the oracle."""
+    _say("case %s full size" % name)
+    params, seeds = workloads.config_inputs(name)
+    count = workloads.CONFIGS[name]["count"]
+    n = params.shape[0]
+    N = mtgp.state_words(int(params[0, 0]))
+    g = mtgp.Generators(params, seeds)
+    out = torch.empty(n * count, dtype=torch.int32, device="cuda")
+    items = [(k, mtgp.U32, count, out.data_ptr() + 4 * k * count) for k in range(n)]
+    ws = g.batch(items)
+    torch.cuda.synchronize()
+    assert mtgp.batch_errors(ws) == 0
+    st = g.states_host()
+    init = np.stack([oracle.seed(int(s), N) for s in seeds])
+    per = 256   # streams per device-to-host copy (1 GiB)
+    cache = {}
+
+    def get(k):
+        blk = k // per
+        if blk not in cache:
+            cache.clear()
+            lo, hi = blk * per * count, min(n, (blk + 1) * per) * count
+            cache[blk] = _host(out[lo:hi])
+        return cache[blk][(k - blk * per) * count:(k - blk * per + 1) * count]
+
+    fin = _compare_streams(get, params, init, count, False, chunk=64)
+    assert np.array_equal(st, fin)
+    del out
+    g.close()
+
+
 def test_zero_counts_leave_streams_untouched(torch):
     """count = 0 is a valid no-op for the plain, workgroup and batch entry
     points: states do not move and the next call continues from the seed."""
