@@ -7,8 +7,9 @@ its seed status on the device, generate 2^24 uint32 outputs per stream,
 re-seed, generate 2^24 float32 outputs per stream from the same initial
 states (both passes through the persistent batch kernel replayed from a
 hipGraph).  Inputs (parameter blocks, seeds) are resident in HBM before
-timing starts.  The default line also carries compact figures of the C3
-and C4 batches and of a shortened C5 serving sweep (--no-extras drops them).
+timing starts.  The default line also carries compact figures of the C3,
+C4 and P1 batches and of a shortened C5 serving sweep (--no-extras drops
+them).
 
 --workload selects the scheduler and serving measurements instead:
   C3  4096 mexp-23209 streams x 2^20 uint32 in one autotuned graph launch
@@ -807,7 +808,7 @@ def run_c5(args):
 def _compact(line):
     keys = ("value", "unit", "ms_per_step", "avg_generate_launch_ms", "roofline",
             "phases_us_prefixjumps_segments_checks", "segment_phase_GBps", "store_only_fill_GBps",
-            "autotuned", "min_step_width", "config")
+            "autotuned", "min_step_width", "polynomials", "config")
     out = {k: line[k] for k in keys if k in line}
     out["autotuned"] = {k: v for k, v in out.get("autotuned", {}).items()
                         if k != "candidate_ms"}
@@ -831,7 +832,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="default workload only: skip the C3, C4 and C5 figures added "
+                    help="default workload only: skip the C3, C4, P1 and C5 figures added "
                          "to the line (profiling runs)")
     ap.add_argument("--extra-requests", type=int, default=4000,
                     help="requests per replay in the C5 figures of the default line")
@@ -853,8 +854,8 @@ def main():
     line = run(args)
     if args.workload == "C2" and not args.no_extras:
         # the scheduler and serving rows in the same run: the autotuned
-        # C3 batch (one graph launch), the autotuned uneven C4 batch and a
-        # shortened C5 sweep
+        # C3 batch (one graph launch), the autotuned uneven C4 batch, the
+        # paper-shaped P1 batch and a shortened C5 sweep
         torch.cuda.empty_cache()
         sub = argparse.Namespace(**vars(args))
         sub.no_cpu_baseline = True
@@ -865,6 +866,10 @@ def main():
         log("C4 (autotuned uneven batch) ...")
         sub.c4_baselines = False  # the one-launch-per-stream runs: --workload C4
         line["C4"] = _compact(run_c4(sub))
+        torch.cuda.empty_cache()
+        log("P1 (the paper's 10,000 statuses at seed 0) ...")
+        sub.workload = "P1"
+        line["P1"] = _compact(run_paper(sub))
         torch.cuda.empty_cache()
         line["C5"] = serve_c5(sub, args.extra_requests, (0.5, 1.0), (0.5, 2.0))
     print(json.dumps(line), flush=True)
