@@ -248,13 +248,16 @@ static mtgp_tuning default_tuning(int N) {
     // W-word steps up to about there), below 64 at N <= 128, where every
     // window is short and the wide path's steps are at most 96 words
     // (measured on 10000 mexp-3217 streams of 2^20 outputs: 22.1 ms against
-    // 23.3 ms with 56 and 29.5 ms with K = 1).
+    // 23.3 ms with 56 and 29.5 ms with K = 1), and below 48 at N = 351
+    // (128 mexp-11213 streams of 2^24 outputs: 2.81 ms against 2.84 ms with
+    // 56, 2.93 with 64 and 2.96 with 40; at N = 726 and 1391 48 and 56
+    // time alike).
     mtgp_tuning t;
     t.threads_per_stream = 64;
     t.workgroup_size = 256;
     t.outputs_per_lane = N <= 400 ? 4 : 8;
     t.jump_target_steps = 1024;
-    t.window_below_w = N <= 128 ? 64 : 56;
+    t.window_below_w = N <= 128 ? 64 : N <= 400 ? 48 : 56;
     return t;
 }
 
