@@ -127,6 +127,16 @@ def test_tuning_tables(lib):
         assert "window_below_w" in str(e.value)
 
 
+def test_default_tunings(lib):
+    # the measured defaults: one wave per stream, 4 waves per workgroup, K = 4
+    # up to N = 400 and 8 above, jump segments of at least 1024 steps, and the
+    # windowed scan below W = 64 (N <= 128), 48 (N = 351) or 56
+    expected = {3217: (64, 4, 256, 1024, 64), 11213: (64, 4, 256, 1024, 48),
+                23209: (64, 8, 256, 1024, 56), 44497: (64, 8, 256, 1024, 56)}
+    for mexp, want in expected.items():
+        assert mtgp.get_tuning(mexp).as_tuple() == want, mexp
+
+
 def test_strerror(lib):
     assert lib.mtgp_strerror(0) == b"ok"
     assert b"pool" in lib.mtgp_strerror(mtgp.ETOOBIG)
