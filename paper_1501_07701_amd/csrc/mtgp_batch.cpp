@@ -666,9 +666,17 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
         a1.counter = hdr + HDR_W_CLAIM;
         a1.groups_per_cu = w.overlap_groups;
         if ((rc = launch_tuned(ps.N, t, a1))) return rc;
-        if ((e = hipEventRecord(w.ev_join, w.aux)) != hipSuccess)
+        if ((e = hipEventRecord(w.ev_join, w.aux)) != hipSuccess) {
+            (void)hipStreamSynchronize(w.aux);  // nothing to order s after: wait here
             return hip_fail(e, "hipEventRecord(join)");
+        }
     }
+    // Once the whole requests run on w.aux, an error return still orders s
+    // after them, so that a caller who sees the error can free the buffers.
+    auto bail = [&](int code) {
+        if (fork) (void)hipStreamWaitEvent(s, w.ev_join, 0);
+        return code;
+    };
     if (w.nA || w.nB) {  // prefix items and jump blocks, one launch
         if ((e = launch_prefix_jumps(ps.N, (const BatchItem *)(ws + w.off_A), w.nA,
                                      (const JumpItem *)(ws + w.off_B), w.nB,
@@ -676,15 +684,17 @@ static int launch_phases(const ParamSet &ps, const void *d_params, char *ws, con
                                      (uint32_t *)(ws + w.off_pflag), (const uint32_t *)d_params,
                                      hdr, (uint32_t)t.window_below_w, device_cus(), s)) !=
             hipSuccess)
-            return hip_fail(e, "prefix and jump kernel");
+            return bail(hip_fail(e, "prefix and jump kernel"));
     }
-    if ((rc = stamp(1))) return rc;
+    if ((rc = stamp(1))) return bail(rc);
     a.items = C;
     a.counter = hdr + 1;
     a.n_items = fork ? w.nCs : w.nC;
-    if ((rc = launch_tuned(ps.N, t, a))) return rc;
-    if (fork && (e = hipStreamWaitEvent(s, w.ev_join, 0)) != hipSuccess)
+    if ((rc = launch_tuned(ps.N, t, a))) return bail(rc);
+    if (fork && (e = hipStreamWaitEvent(s, w.ev_join, 0)) != hipSuccess) {
+        (void)hipStreamSynchronize(w.aux);
         return hip_fail(e, "hipStreamWaitEvent(join)");
+    }
     if ((rc = stamp(2))) return rc;
     if (w.nF) {  // request checks of the split requests
         a.items = (const BatchItem *)(ws + w.off_F);
@@ -986,13 +996,23 @@ int run_batch(const std::shared_ptr<ParamSet> &ps, const void *d_params, uint32_
         if (!(any_split && any_whole)) ov = 0;
     }
     if (ov && !w.aux) {
-        if ((e = hipStreamCreateWithFlags(&w.aux, hipStreamNonBlocking)) != hipSuccess) {
-            w.aux = nullptr;
-            return hip_fail(e, "hipStreamCreate(overlap)");
+        // the second stream and its events, all or none; without them the
+        // batch runs unoverlapped
+        hipStream_t aux = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+            if (j) (void)hipEventDestroy(j);
+            if (f) (void)hipEventDestroy(f);
+            if (aux) (void)hipStreamDestroy(aux);
+            (void)hipGetLastError();
+            ov = 0;
+        } else {
+            w.aux = aux;
+            w.ev_fork = f;
+            w.ev_join = j;
         }
-        if ((e = hipEventCreateWithFlags(&w.ev_fork, hipEventDisableTiming)) != hipSuccess ||
-            (e = hipEventCreateWithFlags(&w.ev_join, hipEventDisableTiming)) != hipSuccess)
-            return hip_fail(e, "hipEventCreate(overlap)");
     }
     w.overlap_groups = ov;
     uint64_t sig = mix(0x51ull, (uint64_t)(uintptr_t)d_params);
