@@ -126,7 +126,10 @@ int mtgp_release_params(const void *d_params);
  * advances streams 0..n_streams-1 of the set by `count_per_stream` outputs
  * each and writes output j of stream k to d_out[k * count_per_stream + j]
  * (stream-major, 64-bit indexing).  d_states rows are updated in place.
- * d_out must hold n_streams * count_per_stream words. */
+ * d_out must hold n_streams * count_per_stream words.  No stream is split
+ * and nothing is allocated, so the call lasts as long as its slowest
+ * stream (the narrowest step width); mtgp_generate_batch with a workspace
+ * sized by mtgp_batch_workspace_query splits long streams by jump-ahead. */
 int mtgp_generate_u32(const void *d_params, uint32_t *d_states,
                       int state_stride, int n_streams,
                       uint64_t count_per_stream, uint32_t *d_out, void *stream);
