@@ -1232,15 +1232,26 @@ hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t s
 }
 
 // Screening statistics over generated uint32 outputs, one workgroup per
-// stream of `count` words at out + k*count (each thread scans a contiguous
-// chunk):
+// stream of `count` words at out + k*count:
 //  gap test (Knuth, Sec. 3.3.2 D, between consecutive hits): a hit is a word
 //    in [lo, hi); the gap between consecutive hits j < j' is j' - j - 1,
 //    counted in bin min(gap, bins-1);
 //  Hamming-weight dependency: the weight class of a word (popcount <= 14,
 //    15..17, >= 18) and of its successor, counted in a 3x3 table.
 // counts[k * (bins + 9) ..] = gap bins, then the table row-major.
-constexpr int SCREEN_THREADS = 256;
+// Wave w takes the region [w R, (w+1) R) of the stream (R a multiple of 64)
+// and reads it 64 consecutive words per load, SCREEN_LOADS loads per pass,
+// so the pass streams from HBM.  In a 64-word slice the hit lanes form a
+// ballot mask: a hit's previous hit is the highest hit lane below it, else
+// the wave's last hit so far.  The weight classes form ballot masks too, and
+// lane l's successor is bit l+1, so the nine pair counts are popcounts of
+// mask products (scalar); a slice's last word pairs with the next slice's
+// first through the carried class.  Gaps and pairs across regions are added
+// at the end, in region order.
+constexpr int SCREEN_WAVES = 4;
+constexpr int SCREEN_THREADS = 64 * SCREEN_WAVES;
+constexpr int SCREEN_LOADS = 8;
+constexpr uint32_t SCREEN_NONE = 0xFFFFFFFFu;  // no hit yet (positions < count < 2^32)
 
 __device__ __forceinline__ uint32_t weight_class(uint32_t v) {
     const uint32_t w = (uint32_t)__builtin_popcount(v);
@@ -1251,43 +1262,86 @@ __global__ void __launch_bounds__(SCREEN_THREADS)
 screen_kernel(const uint32_t *__restrict__ out, uint64_t count, uint32_t lo, uint32_t hi,
               uint32_t bins, uint64_t *__restrict__ counts) {
     __shared__ uint32_t hist[64 + 9];
-    __shared__ int64_t first[SCREEN_THREADS], last[SCREEN_THREADS];
+    __shared__ uint32_t first_hit[SCREEN_WAVES], last_hit[SCREEN_WAVES];
     const uint32_t k = blockIdx.x, tid = threadIdx.x;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63u;
     for (uint32_t i = tid; i < bins + 9; i += SCREEN_THREADS) hist[i] = 0;
     __syncthreads();
     gptr<const uint32_t> x = (gptr<const uint32_t>)(out + (uint64_t)k * count);
-    const uint64_t cs = (count + SCREEN_THREADS - 1) / SCREEN_THREADS;
-    const uint64_t b0 = (uint64_t)tid * cs < count ? (uint64_t)tid * cs : count;
-    const uint64_t b1 = b0 + cs < count ? b0 + cs : count;
-    int64_t f = -1, prev = -1;
-    uint32_t cur = b0 < b1 ? x[b0] : 0u;
-    for (uint64_t j = b0; j < b1; ++j) {
-        const uint32_t nxt = j + 1 < count ? x[j + 1] : 0u;
-        if (lo <= cur && cur < hi) {
-            if (prev >= 0) {
-                const uint64_t gap = j - (uint64_t)prev - 1;
-                atomicAdd(&hist[gap < bins - 1 ? gap : bins - 1], 1u);
-            } else {
-                f = (int64_t)j;
-            }
-            prev = (int64_t)j;
+    const uint64_t R = (count + 64 * SCREEN_WAVES - 1) / (64 * SCREEN_WAVES) * 64;
+    const uint64_t r0 = (uint64_t)wave * R < count ? (uint64_t)wave * R : count;
+    const uint64_t r1 = r0 + R < count ? r0 + R : count;
+    const uint32_t span = hi - lo;  // a hit: v - lo < span
+    const uint64_t lanes_below = lane ? ~0ull >> (64u - lane) : 0ull;
+    uint32_t carry = SCREEN_NONE, first = SCREEN_NONE;
+    uint32_t prev_cls = 3u;  // class of the previous full slice's last word; 3 = none
+    uint32_t hw[9] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};  // wave-uniform pair counts
+    for (uint64_t b0 = r0; b0 < r1; b0 += 64 * SCREEN_LOADS) {
+        uint32_t v[SCREEN_LOADS];
+#pragma unroll
+        for (int e = 0; e < SCREEN_LOADS; ++e) {
+            const uint64_t j = b0 + 64u * e + lane;
+            v[e] = j < r1 ? x[j] : 0u;
         }
-        if (j + 1 < count) atomicAdd(&hist[bins + 3 * weight_class(cur) + weight_class(nxt)], 1u);
-        cur = nxt;
+#pragma unroll
+        for (int e = 0; e < SCREEN_LOADS; ++e) {
+            const uint64_t base = b0 + 64u * e;
+            if (base >= r1) break;  // uniform
+            const uint64_t j = base + lane;
+            const bool valid = j < r1;
+            const bool hit = valid && v[e] - lo < span;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+            if (hit) {
+                const uint64_t bm = m & lanes_below;
+                const uint32_t prev = bm ? (uint32_t)base + 63u - (uint32_t)__builtin_clzll(bm)
+                                         : carry;
+                if (prev != SCREEN_NONE) {
+                    const uint32_t gap = (uint32_t)j - prev - 1u;
+                    atomicAdd(&hist[gap < bins - 1u ? gap : bins - 1u], 1u);
+                }
+            }
+            if (m) {
+                if (first == SCREEN_NONE) first = (uint32_t)base + (uint32_t)__builtin_ctzll(m);
+                carry = (uint32_t)base + 63u - (uint32_t)__builtin_clzll(m);
+            }
+            const uint32_t c = weight_class(v[e]);
+            const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+            const uint64_t m0 = __builtin_amdgcn_ballot_w64(valid && c == 0u);
+            const uint64_t m2 = __builtin_amdgcn_ballot_w64(valid && c == 2u);
+            const uint64_t cm[3] = {m0, vm & ~m0 & ~m2, m2};
+            const uint64_t pairs = vm & (vm >> 1);  // lanes whose successor is in the slice
+            const uint32_t c0 = (m0 & 1u) ? 0u : ((m2 & 1u) ? 2u : 1u);  // lane 0's class
+            const uint32_t cross = prev_cls < 3u ? 3u * prev_cls + c0 : 9u;
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                hw[q] += (uint32_t)__builtin_popcountll(pairs & cm[q / 3] & (cm[q % 3] >> 1)) +
+                         (cross == (uint32_t)q ? 1u : 0u);
+            // a full slice's last word pairs with the next slice's first
+            prev_cls = base + 64u <= r1 ? ((m0 >> 63) ? 0u : ((m2 >> 63) ? 2u : 1u)) : 3u;
+        }
     }
-    first[tid] = f;
-    last[tid] = prev;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) atomicAdd(&hist[bins + q], hw[q]);
+        first_hit[wave] = first;
+        last_hit[wave] = carry;
+    }
     __syncthreads();
     if (tid == 0) {
-        // gaps that span chunk boundaries, in chunk order
-        int64_t pl = -1;
-        for (int t = 0; t < SCREEN_THREADS; ++t) {
-            if (first[t] < 0) continue;
-            if (pl >= 0) {
-                const uint64_t gap = (uint64_t)(first[t] - pl - 1);
-                hist[gap < bins - 1 ? gap : bins - 1] += 1u;
+        // gaps across regions, in region order
+        uint32_t pl = SCREEN_NONE;
+        for (int w = 0; w < SCREEN_WAVES; ++w) {
+            if (first_hit[w] == SCREEN_NONE) continue;
+            if (pl != SCREEN_NONE) {
+                const uint32_t gap = first_hit[w] - pl - 1u;
+                hist[gap < bins - 1u ? gap : bins - 1u] += 1u;
             }
-            pl = last[t];
+            pl = last_hit[w];
+        }
+        // weight pairs across regions
+        for (int w = 0; w + 1 < SCREEN_WAVES; ++w) {
+            const uint64_t e = (uint64_t)(w + 1) * R;
+            if (e < count) hist[bins + 3u * weight_class(x[e - 1]) + weight_class(x[e])] += 1u;
         }
     }
     __syncthreads();
