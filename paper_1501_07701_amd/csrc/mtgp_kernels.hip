@@ -1243,11 +1243,11 @@ hipError_t launch_workgroup(const uint32_t *params, uint32_t *states, uint32_t s
 // and reads it 64 consecutive words per load, SCREEN_LOADS loads per pass,
 // so the pass streams from HBM.  In a 64-word slice the hit lanes form a
 // ballot mask: a hit's previous hit is the highest hit lane below it, else
-// the wave's last hit so far.  The weight classes form ballot masks too, and
-// lane l's successor is bit l+1, so the nine pair counts are popcounts of
-// mask products (scalar); a slice's last word pairs with the next slice's
-// first through the carried class.  Gaps and pairs across regions are added
-// at the end, in region order.
+// the wave's last hit so far.  Each lane counts the weight pair that ends at
+// its word (its predecessor's class from the lane below, lane 0's from the
+// previous slice's last word) in a register of nine 7-bit fields, added
+// into plain counters every 127 slices, so the counting is vector work.
+// Gaps and pairs across regions are added at the end, in region order.
 constexpr int SCREEN_WAVES = 4;
 constexpr int SCREEN_THREADS = 64 * SCREEN_WAVES;
 constexpr int SCREEN_LOADS = 8;
@@ -1275,7 +1275,9 @@ screen_kernel(const uint32_t *__restrict__ out, uint64_t count, uint32_t lo, uin
     const uint64_t lanes_below = lane ? ~0ull >> (64u - lane) : 0ull;
     uint32_t carry = SCREEN_NONE, first = SCREEN_NONE;
     uint32_t prev_cls = 3u;  // class of the previous full slice's last word; 3 = none
-    uint32_t hw[9] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};  // wave-uniform pair counts
+    uint32_t hw[9] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};  // this lane's pair counts
+    uint64_t packed = 0;     // pair counts of the slices since the last flush, 7 bits each
+    uint32_t since = 0;      // slices since the last flush (uniform)
     for (uint64_t b0 = r0; b0 < r1; b0 += 64 * SCREEN_LOADS) {
         uint32_t v[SCREEN_LOADS];
 #pragma unroll
@@ -1304,25 +1306,28 @@ screen_kernel(const uint32_t *__restrict__ out, uint64_t count, uint32_t lo, uin
                 if (first == SCREEN_NONE) first = (uint32_t)base + (uint32_t)__builtin_ctzll(m);
                 carry = (uint32_t)base + 63u - (uint32_t)__builtin_clzll(m);
             }
+            // the pair (j-1, j): j-1's class from the lane below, lane 0's
+            // from the previous slice (3 at the region's start: no pair)
             const uint32_t c = weight_class(v[e]);
-            const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
-            const uint64_t m0 = __builtin_amdgcn_ballot_w64(valid && c == 0u);
-            const uint64_t m2 = __builtin_amdgcn_ballot_w64(valid && c == 2u);
-            const uint64_t cm[3] = {m0, vm & ~m0 & ~m2, m2};
-            const uint64_t pairs = vm & (vm >> 1);  // lanes whose successor is in the slice
-            const uint32_t c0 = (m0 & 1u) ? 0u : ((m2 & 1u) ? 2u : 1u);  // lane 0's class
-            const uint32_t cross = prev_cls < 3u ? 3u * prev_cls + c0 : 9u;
+            const uint32_t below_c = (uint32_t)__shfl_up((int)c, 1, 64);
+            const uint32_t pc = lane ? below_c : prev_cls;
+            if (valid && pc < 3u) packed += 1ull << (7u * (3u * pc + c));
+            // a full slice's last word precedes the next slice's first
+            prev_cls = base + 64u <= r1 ? (uint32_t)__shfl((int)c, 63, 64) : 3u;
+            if (++since == 127u) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
-                hw[q] += (uint32_t)__builtin_popcountll(pairs & cm[q / 3] & (cm[q % 3] >> 1)) +
-                         (cross == (uint32_t)q ? 1u : 0u);
-            // a full slice's last word pairs with the next slice's first
-            prev_cls = base + 64u <= r1 ? ((m0 >> 63) ? 0u : ((m2 >> 63) ? 2u : 1u)) : 3u;
+                for (int q = 0; q < 9; ++q) hw[q] += (uint32_t)(packed >> (7 * q)) & 127u;
+                packed = 0;
+                since = 0;
+            }
         }
     }
-    if (lane == 0) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) atomicAdd(&hist[bins + q], hw[q]);
+    for (int q = 0; q < 9; ++q) {
+        hw[q] += (uint32_t)(packed >> (7 * q)) & 127u;
+        if (hw[q]) atomicAdd(&hist[bins + q], hw[q]);
+    }
+    if (lane == 0) {
         first_hit[wave] = first;
         last_hit[wave] = carry;
     }
